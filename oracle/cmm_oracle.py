@@ -1,0 +1,299 @@
+"""CPU oracle for the compressed matrix product sketch (Pagh, "Compressed
+Matrix Multiplication").
+
+TEST INFRASTRUCTURE.  Only the test-suite, the package's smoke check and the
+benchmark's CPU-baseline leg may import or run this module.  The GPU library
+never calls it, and it shares no code, tables or constants with the GPU path.
+
+Everything here is plain and slow on purpose: float64 numpy, exact Python
+integers for hashing, library primitives (matrix product, sort, bincount) used
+only as single steps, no blocking or reordering beyond what the definitions
+state.  Indices are 0-based (the paper's [n] = {1..n} shifted by one).
+
+What it computes
+----------------
+For d repetitions t, hash functions h1_t, h2_t into {0..b-1} and s1_t, s2_t
+into {-1,+1} define the splitting function h(i,j) = (h1(i)+h2(j)) mod b and
+sign s(i,j) = s1(i)s2(j) (Section 2.2, decomposable hashing).  The sketch of
+the product is the COUNT SKETCH of AB under (h, s):
+
+    c_t[u] = sum over (i,j) with h(i,j) = u of s(i,j) (AB)_ij
+
+(Section 2.2; the estimator analysed in Theorem 2).  Two independent
+formulations are provided and checked against each other:
+
+* ``sketch_from_product`` -- the definition: form AB in float64, bin it.
+* ``sketch_polynomial``   -- the algorithm of Figure 1 without the FFT: for
+  every outer product a_k b_k (eq. (1)) build the two count-sketch
+  polynomials and multiply them modulo x^b - 1 by direct cyclic convolution
+  (the wrap (p mod x^b) + (p div x^b) of the abstract).
+
+Decoding (DECOMPRESS of Figure 1): X_t = s1_t(i) s2_t(j) c_t[h(i,j)], estimate
+= median over t (middle value for odd d, mean of the two middle values for
+even d).  Top-K ranks |C_ij| descending, ties by linear index i*n3+j.
+
+Hash family (Section 2.2, polynomial hashing): g(x) = (a*x + c) mod p with
+p = 2^61 - 1; h = g mod b (b a power of two), s = +1 if g is even else -1.
+Parameters (a, c) per repetition t and function f (h1=0, s1=1, h2=2, s2=3)
+come from the SplitMix64 counter stream (Steele, Lea, Flood 2014) of the
+seed: outputs z_{8t+2f+1}, z_{8t+2f+2}; a = 1 + z mod (p-1), c = z' mod p.
+The paper leaves the source of randomness open; this is the reading chosen.
+
+Parity status of each function is stated in its docstring ("pinned by ...").
+"""
+from __future__ import annotations
+
+import numpy as np
+
+P61 = (1 << 61) - 1
+_M64 = (1 << 64) - 1
+_GAMMA = 0x9E3779B97F4A7C15
+
+
+# ---------------------------------------------------------------------------
+# randomness and hashing
+# ---------------------------------------------------------------------------
+
+def splitmix64(seed: int, count: int) -> list[int]:
+    """First ``count`` outputs z_1..z_count of SplitMix64 seeded with ``seed``.
+
+    Output k mixes the counter seed + k*gamma (mod 2^64) through two
+    xor-shift-multiply rounds and a final xor-shift.  Pinned by published
+    known answers in the tests.
+    """
+    out = []
+    for k in range(1, count + 1):
+        z = (seed + k * _GAMMA) & _M64
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def hash_params(seed: int, d: int) -> np.ndarray:
+    """(d, 4, 2) uint64 array of (a, c) for h1, s1, h2, s2 of each repetition."""
+    z = splitmix64(seed, 8 * d)
+    out = np.zeros((d, 4, 2), dtype=np.uint64)
+    for t in range(d):
+        for f in range(4):
+            za, zc = z[8 * t + 2 * f], z[8 * t + 2 * f + 1]
+            out[t, f, 0] = 1 + za % (P61 - 1)
+            out[t, f, 1] = zc % P61
+    return out
+
+
+def cw_hash(a: int, c: int, xs) -> list[int]:
+    """Carter-Wegman degree-1 polynomial hash (a*x + c) mod (2^61-1), exact."""
+    a, c = int(a), int(c)
+    return [(a * int(x) + c) % P61 for x in xs]
+
+
+def hash_tables(params: np.ndarray, n1: int, n3: int, b: int):
+    """Evaluate h1, s1 on 0..n1-1 and h2, s2 on 0..n3-1 for every repetition.
+
+    Returns int64 arrays h1 (d,n1), s1 (d,n1), h2 (d,n3), s2 (d,n3).
+    """
+    d = params.shape[0]
+    h1 = np.zeros((d, n1), np.int64); s1 = np.zeros((d, n1), np.int64)
+    h2 = np.zeros((d, n3), np.int64); s2 = np.zeros((d, n3), np.int64)
+    for t in range(d):
+        g = cw_hash(params[t, 0, 0], params[t, 0, 1], range(n1)); h1[t] = [v % b for v in g]
+        g = cw_hash(params[t, 1, 0], params[t, 1, 1], range(n1)); s1[t] = [1 - 2 * (v % 2) for v in g]
+        g = cw_hash(params[t, 2, 0], params[t, 2, 1], range(n3)); h2[t] = [v % b for v in g]
+        g = cw_hash(params[t, 3, 0], params[t, 3, 1], range(n3)); s2[t] = [1 - 2 * (v % 2) for v in g]
+    return h1, s1, h2, s2
+
+
+# ---------------------------------------------------------------------------
+# dequantisation of stored operands (float64 values the sketch is of)
+# ---------------------------------------------------------------------------
+
+def _e4m3fn_value(code: int) -> float:
+    """Value of an OCP e4m3fn byte: 1 sign, 4 exponent (bias 7), 3 mantissa
+    bits; exponent 0 is subnormal; S.1111.111 is NaN; no infinities."""
+    sign = -1.0 if code & 0x80 else 1.0
+    e, mnt = (code >> 3) & 0xF, code & 7
+    if e == 15 and mnt == 7:
+        return float("nan")
+    if e == 0:
+        return sign * mnt * 2.0 ** -9
+    return sign * (8 + mnt) * 2.0 ** (e - 10)
+
+
+_E4M3_TABLE = np.array([_e4m3fn_value(c) for c in range(256)])
+
+
+def dequantise(stored: np.ndarray, dtype: str, scale=None) -> np.ndarray:
+    """float64 values of a stored k-major operand (f32 / bf16 bits / fp8 bits
+    times a per-column scale)."""
+    if dtype == "f32":
+        return np.asarray(stored, dtype=np.float64)
+    if dtype == "bf16":
+        bits = np.asarray(stored, dtype=np.uint16).astype(np.uint32) << np.uint32(16)
+        return bits.view(np.float32).astype(np.float64)
+    if dtype == "fp8":
+        v = _E4M3_TABLE[np.asarray(stored, dtype=np.uint8).astype(np.int64)]
+        if scale is not None:
+            v = v * np.asarray(scale, dtype=np.float32).astype(np.float64)[None, :]
+        return v
+    raise ValueError(dtype)
+
+
+# ---------------------------------------------------------------------------
+# the sketch
+# ---------------------------------------------------------------------------
+
+def countsketch(v: np.ndarray, h: np.ndarray, s: np.ndarray, b: int) -> np.ndarray:
+    """COUNT SKETCH of a weighted vector (Section 2.2): p[u] = sum_{h(i)=u}
+    s(i) v_i, i.e. the coefficients of the polynomial p_v^{h,s}(x).
+    Pinned by brute force in the tests."""
+    p = np.zeros(b)
+    np.add.at(p, h, s * v)
+    return p
+
+
+def cyclic_convolution(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """(x * y) mod (z^b - 1) by the direct double sum over nonzero terms:
+    out[(u+w) mod b] += x[u] y[w].  No FFT."""
+    b = x.shape[0]
+    ux, uy = np.nonzero(x)[0], np.nonzero(y)[0]
+    if ux.size == 0 or uy.size == 0:
+        return np.zeros(b)
+    idx = (ux[:, None] + uy[None, :]) % b
+    return np.bincount(idx.ravel(), weights=np.outer(x[ux], y[uy]).ravel(), minlength=b)
+
+
+def sketch_polynomial(A: np.ndarray, B: np.ndarray, tables, b: int) -> np.ndarray:
+    """Figure 1's COMPRESSEDPRODUCT with the FFT product replaced by direct
+    cyclic convolution: for each repetition t and each k, convolve the count
+    sketches of column a_k (h1, s1) and row b_k (h2, s2) and sum over k.
+    Returns c (d, b).  Pinned against ``sketch_from_product`` and, for
+    injective hashes, against the plain matrix product."""
+    h1, s1, h2, s2 = tables
+    d = h1.shape[0]
+    c = np.zeros((d, b))
+    for t in range(d):
+        for k in range(A.shape[1]):
+            pa = countsketch(A[:, k], h1[t], s1[t], b)
+            pb = countsketch(B[k, :], h2[t], s2[t], b)
+            c[t] += cyclic_convolution(pa, pb)
+    return c
+
+
+def bin_product(AB: np.ndarray, tables, b: int, row_block: int = 1024) -> np.ndarray:
+    """Bin a given n1-by-n3 matrix M by h(i,j) with sign s(i,j): the COUNT
+    SKETCH definition applied to M (rows processed in blocks to bound memory)."""
+    h1, s1, h2, s2 = tables
+    d = h1.shape[0]
+    n1 = AB.shape[0]
+    c = np.zeros((d, b))
+    for t in range(d):
+        for r0 in range(0, n1, row_block):
+            r1 = min(n1, r0 + row_block)
+            idx = (h1[t, r0:r1, None] + h2[t, None, :]) % b
+            w = (s1[t, r0:r1, None] * s2[t, None, :]) * AB[r0:r1]
+            c[t] += np.bincount(idx.ravel(), weights=w.ravel(), minlength=b)
+    return c
+
+
+def sketch_from_product(A: np.ndarray, B: np.ndarray, tables, b: int) -> np.ndarray:
+    """The definition: c_t[u] = sum_{h(i,j)=u} s(i,j) (AB)_ij with AB formed
+    exactly in float64.  Pinned by brute-force loops on tiny inputs."""
+    AB = np.asarray(A, dtype=np.float64) @ np.asarray(B, dtype=np.float64)
+    return bin_product(AB, tables, b)
+
+
+def subtract_diagonal(c: np.ndarray, diag: np.ndarray, tables, b: int) -> np.ndarray:
+    """Sketch of AB with its diagonal zeroed (Section 3.2, Q-tilde): remove
+    s1(i)s2(i)(AB)_ii from bucket h(i,i) of every repetition."""
+    h1, s1, h2, s2 = tables
+    out = c.copy()
+    n = diag.shape[0]
+    for t in range(c.shape[0]):
+        idx = (h1[t, :n] + h2[t, :n]) % b
+        np.add.at(out[t], idx, -(s1[t, :n] * s2[t, :n]) * diag)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# decoding, median, top-K
+# ---------------------------------------------------------------------------
+
+def median(x: np.ndarray, axis: int = 0) -> np.ndarray:
+    """Median along ``axis``: middle order statistic for odd length, mean of
+    the two middle ones for even length."""
+    x = np.sort(x, axis=axis)
+    d = x.shape[axis]
+    lo = np.take(x, (d - 1) // 2, axis=axis)
+    hi = np.take(x, d // 2, axis=axis)
+    return lo if d % 2 else 0.5 * (lo + hi)
+
+
+def decode(c: np.ndarray, tables, i, j) -> np.ndarray:
+    """DECOMPRESS(i, j) of Figure 1 for arrays of index pairs: median over t
+    of s1_t(i) s2_t(j) c_t[(h1_t(i) + h2_t(j)) mod b]."""
+    h1, s1, h2, s2 = tables
+    b = c.shape[1]
+    i, j = np.broadcast_arrays(np.asarray(i, dtype=np.int64), np.asarray(j, dtype=np.int64))
+    X = np.empty((c.shape[0],) + i.shape)
+    for t in range(c.shape[0]):
+        X[t] = s1[t, i] * s2[t, j] * c[t, (h1[t, i] + h2[t, j]) % b]
+    return median(X, axis=0)
+
+
+def candidates(mode: str, n1: int, n3: int):
+    """Linear indices i*n3+j of the candidate domain: all entries, or i<j."""
+    i, j = np.meshgrid(np.arange(n1), np.arange(n3), indexing="ij")
+    if mode == "upper":
+        keep = i < j
+        return i[keep], j[keep]
+    return i.ravel(), j.ravel()
+
+
+def topk(values: np.ndarray, lin: np.ndarray, K: int):
+    """First K of (values, lin) sorted by |value| descending, then lin
+    ascending.  Returns (lin, values) of the selection."""
+    order = np.lexsort((lin, -np.abs(values)))[:K]
+    return lin[order], values[order]
+
+
+def topk_per_column(C: np.ndarray, K: int):
+    """For every column j of an n1-by-n3 estimate matrix, the K rows with the
+    largest |C_ij| (ties by smaller i).  Returns (rows (n3,K), vals (n3,K))."""
+    n1, n3 = C.shape
+    rows = np.empty((n3, K), np.int64); vals = np.empty((n3, K))
+    ii = np.arange(n1)
+    for j in range(n3):
+        o = np.lexsort((ii, -np.abs(C[:, j])))[:K]
+        rows[j] = o; vals[j] = C[o, j]
+    return rows, vals
+
+
+def decode_all(c: np.ndarray, tables, n1: int, n3: int, row_block: int = 512) -> np.ndarray:
+    """All n1*n3 estimates (only for sizes where that fits in memory)."""
+    out = np.empty((n1, n3))
+    jj = np.arange(n3)
+    for r0 in range(0, n1, row_block):
+        r1 = min(n1, r0 + row_block)
+        ii = np.arange(r0, r1)
+        out[r0:r1] = decode(c, tables, ii[:, None], jj[None, :])
+    return out
+
+
+# ---------------------------------------------------------------------------
+# a whole product, as the GPU path is asked for it
+# ---------------------------------------------------------------------------
+
+def run(A: np.ndarray, B: np.ndarray, b: int, d: int, seed: int, subtract_diag: bool = False,
+        params: np.ndarray | None = None, tables=None):
+    """Sketch of AB (definition form) for ``d`` repetitions; returns
+    (c, tables, AB)."""
+    n1, n3 = A.shape[0], B.shape[1]
+    if tables is None:
+        params = hash_params(seed, d) if params is None else params
+        tables = hash_tables(params, n1, n3, b)
+    AB = np.asarray(A, dtype=np.float64) @ np.asarray(B, dtype=np.float64)
+    c = bin_product(AB, tables, b)
+    if subtract_diag:
+        c = subtract_diagonal(c, np.diag(AB).copy(), tables, b)
+    return c, tables, AB

@@ -1,0 +1,304 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+None of these compare the oracle with itself: each checks a function against
+a known answer, a closed form, a theorem of the paper, brute force, or an
+independent formulation that shares no code with it.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cmm_oracle as O
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- randomness
+
+def test_splitmix64_known_answers():
+    with open(os.path.join(GOLDEN, "splitmix64_kat.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    for row in rows:
+        seed = int(row[0], 0)
+        want = [int(x, 0) for x in row[1:]]
+        assert O.splitmix64(seed, len(want)) == want
+
+
+def test_hash_params_ranges():
+    pr = O.hash_params(12345, 7)
+    assert pr.shape == (7, 4, 2)
+    a = pr[:, :, 0].astype(object); c = pr[:, :, 1].astype(object)
+    assert all(1 <= int(x) < O.P61 for x in a.ravel())
+    assert all(0 <= int(x) < O.P61 for x in c.ravel())
+    # 8d distinct stream outputs feed 8d distinct parameters
+    assert len({int(x) for x in pr.ravel()}) == 8 * 7
+
+
+def _mersenne_mod(v: int) -> int:
+    """v mod (2^61-1) by repeated folding of 61-bit digits (an independent
+    route to the same residue)."""
+    while v >> 61:
+        v = (v & O.P61) + (v >> 61)
+    return 0 if v == O.P61 else v
+
+
+def test_cw_hash_known_values():
+    assert O.cw_hash(3, 5, [7]) == [26]
+    p = O.P61
+    assert O.cw_hash(p - 1, p - 1, [2]) == [p - 3]          # 3(p-1) = 3p - 3
+    assert O.cw_hash(1, 0, [p, p + 1]) == [0, 1]
+    g = np.random.default_rng(0)
+    for _ in range(200):
+        a = int(g.integers(1, 2**61 - 1)); c = int(g.integers(0, 2**61 - 1)); x = int(g.integers(0, 2**32))
+        assert O.cw_hash(a, c, [x])[0] == _mersenne_mod(a * x + c)
+
+
+def test_hash_tables_definition():
+    pr = O.hash_params(7, 2)
+    h1, s1, h2, s2 = O.hash_tables(pr, 10, 9, 64)
+    for t in range(2):
+        for x in range(10):
+            g = (int(pr[t, 0, 0]) * x + int(pr[t, 0, 1])) % O.P61
+            assert h1[t, x] == g & 63
+            gs = (int(pr[t, 1, 0]) * x + int(pr[t, 1, 1])) % O.P61
+            assert s1[t, x] == (1 if gs % 2 == 0 else -1)
+
+
+def test_hash_pairwise_collisions():
+    """2-wise independence (Section 2.2): over random parameters a pair of
+    distinct keys collides with probability ~1/b, and a sign pair agrees
+    with probability ~1/2."""
+    b, trials = 16, 4000
+    coll = agree = 0
+    for s in range(trials):
+        pr = O.hash_params(10_000 + s, 1)
+        h1, s1, _, _ = O.hash_tables(pr, 6, 1, b)
+        coll += int(h1[0, 2] == h1[0, 5])
+        agree += int(s1[0, 1] == s1[0, 4])
+    p = coll / trials
+    assert abs(p - 1 / b) < 4 * math.sqrt((1 / b) * (1 - 1 / b) / trials)
+    q = agree / trials
+    assert abs(q - 0.5) < 4 * math.sqrt(0.25 / trials)
+
+
+# ------------------------------------------------------------- dequantising
+
+def test_e4m3fn_known_values():
+    # OCP 8-bit floating point spec, E4M3: max normal 448, min normal 2^-6,
+    # min subnormal 2^-9, 0x7f / 0xff are NaN.
+    v = O.dequantise(np.array([[0x7E, 0x08, 0x01, 0x38, 0xB8, 0x00, 0x80, 0x7F]], np.uint8), "fp8")[0]
+    assert v[0] == 448.0 and v[1] == 2.0 ** -6 and v[2] == 2.0 ** -9
+    assert v[3] == 1.0 and v[4] == -1.0 and v[5] == 0.0 and v[6] == 0.0
+    assert math.isnan(v[7])
+    # the encoder of the input generator inverts the decoder on every finite code
+    codes = np.array([c for c in range(256) if (c & 0x7F) != 0x7F], np.uint8)
+    vals = O.dequantise(codes[None, :], "fp8")[0]
+    back = W.e4m3fn_encode(vals)
+    same = (back == codes) | ((vals == 0) & ((back & 0x7F) == 0))
+    assert same.all()
+
+
+def test_bf16_known_values():
+    v = O.dequantise(np.array([[0x3F80, 0xC000, 0x0000, 0x7F7F]], np.uint16), "bf16")[0]
+    assert v[0] == 1.0 and v[1] == -2.0 and v[2] == 0.0
+    assert v[3] == float(np.float32(3.3895313892515355e38))
+
+
+# ------------------------------------------------------------------ sketch
+
+def test_countsketch_bruteforce():
+    g = np.random.default_rng(1)
+    v = g.standard_normal(40); h = g.integers(0, 8, 40); s = g.choice([-1, 1], 40)
+    p = O.countsketch(v, h, s, 8)
+    for u in range(8):
+        acc = 0.0
+        for i in range(40):
+            if h[i] == u:
+                acc += s[i] * v[i]
+        assert abs(p[u] - acc) < 1e-12
+
+
+def test_hand_worked_example():
+    A = np.array([[1.0], [2.0]]); B = np.array([[3.0, 4.0]])
+    h1 = np.array([[0, 1]]); h2 = np.array([[0, 1]])
+    with open(os.path.join(GOLDEN, "hand_sketch.txt")) as f:
+        rows = [[int(x) for x in l.split()] for l in f if l.strip() and not l.startswith("#")]
+    for s10, s11, s20, s21, c0, c1 in rows:
+        tabs = (h1, np.array([[s10, s11]]), h2, np.array([[s20, s21]]))
+        for fn in (O.sketch_from_product, O.sketch_polynomial):
+            c = fn(A, B, tabs, 2)
+            assert c[0].tolist() == [c0, c1]
+
+
+def _brute_sketch(A, B, tabs, b):
+    h1, s1, h2, s2 = tabs
+    d = h1.shape[0]
+    n1, m = A.shape; n3 = B.shape[1]
+    c = [[0.0] * b for _ in range(d)]
+    for t in range(d):
+        for i in range(n1):
+            for j in range(n3):
+                ab = 0.0
+                for k in range(m):
+                    ab += float(A[i, k]) * float(B[k, j])
+                u = (int(h1[t, i]) + int(h2[t, j])) % b
+                c[t][u] += int(s1[t, i]) * int(s2[t, j]) * ab
+    return np.array(c)
+
+
+def test_definition_bruteforce():
+    g = np.random.default_rng(2)
+    A = g.standard_normal((5, 4)); B = g.standard_normal((4, 6))
+    tabs = O.hash_tables(O.hash_params(99, 3), 5, 6, 8)
+    np.testing.assert_allclose(O.sketch_from_product(A, B, tabs, 8), _brute_sketch(A, B, tabs, 8),
+                               rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape,b,d", [((13, 7, 11), 16, 3), ((32, 9, 20), 64, 2), ((20, 20, 20), 16, 1)])
+def test_polynomial_equals_definition(shape, b, d):
+    n1, m, n3 = shape
+    g = np.random.default_rng(n1 * 100 + b)
+    A = g.standard_normal((n1, m)); B = g.standard_normal((m, n3))
+    tabs = O.hash_tables(O.hash_params(5 + b, d), n1, n3, b)
+    c1 = O.sketch_polynomial(A, B, tabs, b)
+    c2 = O.sketch_from_product(A, B, tabs, b)
+    np.testing.assert_allclose(c1, c2, rtol=0, atol=1e-11 * np.abs(c2).max())
+
+
+def test_injective_hashes_recover_product():
+    """h1(i) = i, h2(j) = n1*j, s = +1 and b >= n1*n3 make the splitting
+    function injective, so the sketch holds AB itself (c[i + n1 j] = (AB)_ij)
+    and decoding returns AB.  Checked against numpy's matrix product; the
+    polynomial form uses no matrix product."""
+    n1, m, n3 = 6, 5, 7
+    b = 64
+    g = np.random.default_rng(3)
+    A = g.standard_normal((n1, m)); B = g.standard_normal((m, n3))
+    tabs = (np.arange(n1)[None, :], np.ones((1, n1), np.int64),
+            (n1 * np.arange(n3))[None, :], np.ones((1, n3), np.int64))
+    c = O.sketch_polynomial(A, B, tabs, b)
+    AB = A @ B
+    for i in range(n1):
+        for j in range(n3):
+            assert abs(c[0, i + n1 * j] - AB[i, j]) < 1e-12
+    C = O.decode_all(c, tabs, n1, n3)
+    np.testing.assert_allclose(C, AB, rtol=0, atol=1e-12)
+
+
+def test_b1_is_ams_sketch():
+    """b = 1: every pair shares the one bucket, so the sketch is the AMS
+    sketch of AB, the sum over k of (s1 . a_k)(s2 . b_k) (Section 2.1)."""
+    g = np.random.default_rng(4)
+    A = g.standard_normal((9, 8)); B = g.standard_normal((8, 10))
+    tabs = O.hash_tables(O.hash_params(17, 2), 9, 10, 1)
+    for fn in (O.sketch_from_product, O.sketch_polynomial):
+        c = fn(A, B, tabs, 1)
+        for t in range(2):
+            ams = sum(float(tabs[1][t] @ A[:, k]) * float(B[k, :] @ tabs[3][t]) for k in range(8))
+            assert abs(c[t, 0] - ams) < 1e-11
+
+
+def test_k_split_linearity():
+    """The sketch is linear in the outer products (eq. (1)): splitting k
+    into two ranges and adding the sketches gives the whole sketch."""
+    g = np.random.default_rng(5)
+    A = g.standard_normal((10, 12)); B = g.standard_normal((12, 9))
+    tabs = O.hash_tables(O.hash_params(23, 2), 10, 9, 32)
+    whole = O.sketch_polynomial(A, B, tabs, 32)
+    part = O.sketch_polynomial(A[:, :5], B[:5], tabs, 32) + O.sketch_polynomial(A[:, 5:], B[5:], tabs, 32)
+    np.testing.assert_allclose(whole, part, rtol=0, atol=1e-12)
+
+
+def test_subtract_diagonal_matches_binning_zeroed_diagonal():
+    g = np.random.default_rng(6)
+    X = g.standard_normal((11, 8))
+    A, B = X.T, X
+    tabs = O.hash_tables(O.hash_params(31, 3), 8, 8, 16)
+    c, _, AB = O.run(A, B, 16, 3, 0, subtract_diag=True, tables=tabs)
+    Z = AB - np.diag(np.diag(AB))
+    np.testing.assert_allclose(c, O.bin_product(Z, tabs, 16), rtol=0, atol=1e-11)
+
+
+# -------------------------------------------------------------- decoding
+
+def test_median_conventions():
+    x = np.array([[3.0, 1.0], [1.0, 4.0], [2.0, 1.0]])
+    assert O.median(x, 0).tolist() == [2.0, 1.0]
+    y = np.array([[4.0], [1.0], [3.0], [2.0]])
+    assert O.median(y, 0).tolist() == [2.5]
+    g = np.random.default_rng(7)
+    for d in range(1, 12):
+        z = g.standard_normal((d, 50))
+        np.testing.assert_array_equal(O.median(z, 0), np.median(z, axis=0))
+
+
+def test_topk_order_and_ties():
+    vals = np.array([1.0, -3.0, 3.0, 0.5, -3.0, 2.0])
+    lin = np.array([10, 4, 7, 1, 2, 3])
+    sel_lin, sel_val = O.topk(vals, lin, 4)
+    assert sel_lin.tolist() == [2, 4, 7, 3]
+    assert sel_val.tolist() == [-3.0, -3.0, 3.0, 2.0]
+
+
+def test_theorem2_unbiased_and_variance():
+    """Theorem 2: with d = 1 the estimate is unbiased and its variance is at
+    most ||AB||_F^2 / b; for a pairwise-independent splitting function it is
+    close to (||AB||_F^2 - AB_ij^2) / b."""
+    g = np.random.default_rng(8)
+    A = g.standard_normal((6, 5)); B = g.standard_normal((5, 7))
+    AB = A @ B
+    b, S = 16, 3000
+    i, j = 2, 3
+    est = np.empty(S)
+    for s in range(S):
+        tabs = O.hash_tables(O.hash_params(50_000 + s, 1), 6, 7, b)
+        c = O.sketch_from_product(A, B, tabs, b)
+        est[s] = O.decode(c, tabs, [i], [j])[0]
+    fro2 = float((AB ** 2).sum())
+    se = math.sqrt(fro2 / b / S)
+    assert abs(est.mean() - AB[i, j]) < 4 * se
+    var = est.var(ddof=1)
+    assert var <= fro2 / b * 1.15
+    assert abs(var - (fro2 - AB[i, j] ** 2) / b) < 0.15 * fro2 / b
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_theorem5_sparse_product_exact(seed):
+    """Theorem 5: AB with at most b/8 nonzeros and d >= 6 lg n is decoded
+    exactly.  The product is sparse only through cancellation: A = Q random
+    orthogonal, B = Q^T S."""
+    n = 32
+    g = np.random.default_rng(100 + seed)
+    Q, _ = np.linalg.qr(g.standard_normal((n, n)))
+    S = np.zeros((n, n))
+    pos = g.choice(n * n, size=16, replace=False)
+    S.flat[pos] = g.standard_normal(16) * 10
+    A, B = Q, Q.T @ S
+    b = 128                                   # 16 nonzeros = b/8
+    d = int(math.ceil(6 * math.log2(n))) | 1  # 31
+    c, tabs, AB = O.run(A, B, b, d, 900 + seed)
+    C = O.decode_all(c, tabs, n, n)
+    assert np.abs(C - S).max() < 1e-9 * np.abs(S).max()
+
+
+def test_theorem6_tail_bound():
+    """Theorem 6: with d >= 6 lg n every estimate is within
+    12 sqrt(Err_F^{b/20}(AB) / b) of AB."""
+    n = 32
+    g = np.random.default_rng(200)
+    A = g.standard_normal((n, n)); B = g.standard_normal((n, n)) * 0.05
+    B += np.eye(n) * 0                        # keep B generic
+    P = np.zeros((n, n)); P.flat[g.choice(n * n, 12, replace=False)] = 40.0
+    AB_target = A @ B + P
+    B2 = np.linalg.solve(A, AB_target)        # A @ B2 = AB_target
+    b = 256
+    d = int(math.ceil(6 * math.log2(n))) | 1
+    c, tabs, AB = O.run(A, B2, b, d, 321)
+    C = O.decode_all(c, tabs, n, n)
+    mags = np.sort(np.abs(AB).ravel())[::-1]
+    err_f = float((mags[b // 20:] ** 2).sum())
+    bound = 12 * math.sqrt(err_f / b)
+    assert np.abs(C - AB).max() < bound
