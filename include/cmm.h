@@ -1,0 +1,179 @@
+/*
+ * cmm.h -- compressed matrix multiplication on one MI355X (gfx950).
+ *
+ * C interface to the sketch of a matrix product from R. Pagh, "Compressed
+ * Matrix Multiplication".  For d independent repetitions t the library
+ * computes the length-b count sketch of AB
+ *
+ *     c_t[u] = sum over (i,j) with (h1_t(i) + h2_t(j)) mod b = u
+ *              of s1_t(i) s2_t(j) (AB)_ij                       (Section 2.2)
+ *
+ * without forming AB: every outer product a_k b_k of eq. (1) is count-
+ * sketched on both sides, the two sketches are multiplied as polynomials
+ * modulo x^b - 1 through the FFT, and the products are summed over k before
+ * one inverse FFT per repetition (Figure 1, COMPRESSEDPRODUCT).  Entries are
+ * decoded as the median over t of s1_t(i) s2_t(j) c_t[(h1_t(i)+h2_t(j)) mod b]
+ * (Figure 1, DECOMPRESS) and the largest ones are selected.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every function returns an int status: CMM_OK (0) or a negative CMM_E*
+ *   code.  No exception crosses the interface.  cmm_strerror() names a code;
+ *   cmm_last_error() gives the message of the context's last failure.
+ * - Matrix operands are caller-owned DEVICE pointers, read only, and must
+ *   stay valid until the call returns (or, with CMM_ASYNC, until the context
+ *   stream has passed the call).  They are laid out in the single-pass order
+ *   of Section 2.2: A (n1 x m) column-major, i.e. A[i,k] at A[k*lda + i]
+ *   with lda >= n1; B (m x n3) row-major, B[k,j] at B[k*ldb + j] with
+ *   ldb >= n3.  For a sample covariance product A = X^T, B = X, both are the
+ *   m-by-n observation matrix X (one row per sample, Section 3.2).
+ * - Work is ordered on the context's HIP stream.  Calls return after the
+ *   stream has finished unless CMM_ASYNC is passed.
+ * - Hashing (Section 2.2, polynomial hash functions): g(x) = (a x + c) mod
+ *   (2^61 - 1); h = g mod b; s = +1 if g is even, -1 if odd; one (a, c) pair
+ *   per repetition and per function h1, s1, h2, s2 (in that order).  With a
+ *   seed the pairs come from the SplitMix64 stream of the seed: outputs
+ *   z_{8t+2f+1}, z_{8t+2f+2} give a = 1 + z mod (2^61-2), c = z' mod (2^61-1).
+ * - b must be a power of two in [16, 2^22]; 1 <= d <= 63.
+ * - Objects are library-owned: free sketches with cmm_sketch_free() before
+ *   destroying their context with cmm_ctx_destroy().
+ */
+#ifndef CMM_H
+#define CMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CMM_OK            0
+#define CMM_EINVAL       -1  /* an argument is out of its documented range */
+#define CMM_ENOMEM       -2  /* device memory could not be allocated */
+#define CMM_EHIP         -3  /* a HIP runtime call or kernel launch failed */
+#define CMM_EUNSUPPORTED -4  /* valid request outside what this build handles */
+#define CMM_ESTATE       -5  /* object in the wrong state (freed, mismatched) */
+
+/* element types of the stored operands */
+#define CMM_F32       0      /* IEEE binary32 */
+#define CMM_BF16      1      /* bfloat16 bits (uint16) */
+#define CMM_FP8_E4M3  2      /* OCP e4m3fn bits (uint8) times a per-column scale */
+
+/* flags of cmm_sketch_product_ex */
+#define CMM_SUBTRACT_DIAG 1u /* sketch AB with its diagonal zeroed (n1 == n3) */
+#define CMM_ASYNC         2u /* do not wait for the stream before returning */
+
+/* candidate domains of cmm_topk */
+#define CMM_TOPK_ALL        0 /* every (i, j) */
+#define CMM_TOPK_UPPER      1 /* i < j only (symmetric products) */
+#define CMM_TOPK_PER_COLUMN 2 /* the K largest of every column j, n3*K results */
+
+typedef struct cmm_ctx cmm_ctx;
+typedef struct cmm_sketch cmm_sketch;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device` whose work is ordered on
+ * `hip_stream` (a hipStream_t; NULL = the device's null stream).  The
+ * context owns a cache of device buffers reused across calls. */
+int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out);
+
+/* Switch the context to another stream; waits for the old one first. */
+int cmm_ctx_set_stream(cmm_ctx* ctx, void* hip_stream);
+
+/* Wait for the stream, release every cached buffer and the context. */
+int cmm_ctx_destroy(cmm_ctx* ctx);
+
+const char* cmm_strerror(int code);
+const char* cmm_last_error(const cmm_ctx* ctx);
+
+/* Kernel timing: while enabled, the library records a pair of HIP events on
+ * the context stream around every launch of the named kernels and sums
+ * their durations.  `name` is one of "hash", "layout", "countsketch",
+ * "fft_mac", "ifft", "decode".  Reading waits for the stream. */
+int cmm_ctx_profile(cmm_ctx* ctx, int enable);
+int cmm_ctx_profile_read(cmm_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
+
+/* ---- the sketch (COMPRESSEDPRODUCT, Figure 1) ------------------------- */
+
+/* Square float32 form: A (n x n, column-major, lda = n), B (n x n,
+ * row-major, ldb = n), b buckets, d repetitions, hash seed.  On success
+ * *out holds the sketch c[d][b] on the device. */
+int cmm_sketch_product(cmm_ctx* ctx, const float* A, const float* B, int64_t n,
+                       int64_t b, int32_t d, uint64_t seed, cmm_sketch** out);
+
+/* General form.  `dtype` is CMM_F32, CMM_BF16 or CMM_FP8_E4M3; for fp8,
+ * scaleA (n1 floats, device) scales A's row i and scaleB (n3 floats,
+ * device) scales B's column j (the stored arrays' column scales); NULL means
+ * 1.  `hash_params` (host, d*4*2 uint64 (a, c) pairs in the order h1, s1,
+ * h2, s2, with 1 <= a < 2^61-1 and c < 2^61-1) replaces the seed-derived
+ * parameters when non-NULL.  `flags` combines CMM_SUBTRACT_DIAG (requires
+ * n1 == n3; subtracts s1(i)s2(i)(AB)_ii from bucket (h1(i)+h2(i)) mod b,
+ * giving the sketch of the product with a zero diagonal, Section 3.2) and
+ * CMM_ASYNC. */
+int cmm_sketch_product_ex(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                          int64_t n1, int64_t m, int64_t n3, int32_t dtype,
+                          const float* scaleA, const float* scaleB, int64_t b, int32_t d,
+                          uint64_t seed, const uint64_t* hash_params, uint32_t flags,
+                          cmm_sketch** out);
+
+/* Same product with explicit hash tables instead of hash functions (host
+ * arrays: h1[d*n1] in [0,b), s1[d*n1] in {-1,+1}, h2[d*n3], s2[d*n3]).
+ * Meant for tests that need a chosen splitting function, e.g. an injective
+ * one that turns the sketch into the plain product. */
+int cmm_sketch_product_tables(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                              int64_t n1, int64_t m, int64_t n3, int32_t dtype,
+                              const float* scaleA, const float* scaleB, int64_t b, int32_t d,
+                              const int32_t* h1, const int8_t* s1, const int32_t* h2,
+                              const int8_t* s2, uint32_t flags, cmm_sketch** out);
+
+int cmm_sketch_free(cmm_sketch* sk);
+
+/* Dimensions of a sketch (any output pointer may be NULL). */
+int cmm_sketch_info(const cmm_sketch* sk, int64_t* n1, int64_t* m, int64_t* n3,
+                    int64_t* b, int32_t* d);
+
+/* Copy c[t][u] (row-major d x b, float64) to `dst`, `count` = d*b; dst is a
+ * device pointer when dst_on_device != 0, else host memory. */
+int cmm_sketch_copy_c(const cmm_sketch* sk, double* dst, int64_t count, int32_t dst_on_device);
+
+/* Host copies of the hash parameters (d*4*2 uint64) and of repetition t's
+ * hash tables (h1[n1], s1[n1], h2[n3], s2[n3]; any pointer may be NULL). */
+int cmm_sketch_hash_params(const cmm_sketch* sk, uint64_t* ac);
+int cmm_sketch_hashes(const cmm_sketch* sk, int32_t t, int32_t* h1, int8_t* s1,
+                      int32_t* h2, int8_t* s2);
+
+/* Linear updates of a sketch (Section 3.2 and eq. (1)): subtract the
+ * diagonal diag[0..len) (device float64, len <= min(n1, n3)) from every
+ * repetition; add another sketch of the same (hash parameters, b, d, n1,
+ * n3), e.g. one taken over a different range of k.  CMM_ESTATE if they do
+ * not match. */
+int cmm_sketch_subtract_diagonal(cmm_sketch* sk, const double* diag, int64_t len);
+int cmm_sketch_merge(cmm_sketch* dst, const cmm_sketch* src);
+
+/* ---- decoding (DECOMPRESS, Figure 1) ---------------------------------- */
+
+/* Estimate of (AB)_ij: median over t of s1_t(i) s2_t(j) c_t[(h1_t(i) +
+ * h2_t(j)) mod b]; for even d the mean of the two middle values.  Result in
+ * host memory. */
+int cmm_estimate(const cmm_sketch* sk, int64_t i, int64_t j, double* out);
+
+/* Batched estimates of q pairs (device arrays i[q], j[q]; device out[q]). */
+int cmm_estimate_batch(const cmm_sketch* sk, const int64_t* i, const int64_t* j, int64_t q,
+                       float* out);
+
+/* The K estimates of largest magnitude in the candidate domain `mode`,
+ * ordered by |C_ij| descending and then by linear index i*n3 + j ascending
+ * (ties between equal magnitudes therefore resolve to the smaller index).
+ * Outputs are host arrays of K entries (n3*K for CMM_TOPK_PER_COLUMN, column
+ * j's results at [j*K, (j+1)*K)).  The estimates are decoded on the device
+ * and never stored as a whole matrix. */
+int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int64_t* out_j,
+             float* out_val);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMM_H */

@@ -132,10 +132,12 @@ def dequantise(stored: np.ndarray, dtype: str, scale=None) -> np.ndarray:
         bits = np.asarray(stored, dtype=np.uint16).astype(np.uint32) << np.uint32(16)
         return bits.view(np.float32).astype(np.float64)
     if dtype == "fp8":
-        v = _E4M3_TABLE[np.asarray(stored, dtype=np.uint8).astype(np.int64)]
+        # an element's value is the float32 product of its decoded code and
+        # its column scale
+        v = _E4M3_TABLE[np.asarray(stored, dtype=np.uint8).astype(np.int64)].astype(np.float32)
         if scale is not None:
-            v = v * np.asarray(scale, dtype=np.float32).astype(np.float64)[None, :]
-        return v
+            v = v * np.asarray(scale, dtype=np.float32)[None, :]
+        return v.astype(np.float64)
     raise ValueError(dtype)
 
 

@@ -1,0 +1,328 @@
+"""Python binding of the cmm HIP library (libcmm.so).
+
+Argument marshalling only: every step of the sketch product, decoding and
+selection runs in the library's HIP kernels.  Functions carry the C names
+(``cmm_sketch_product`` ...) and take torch tensors for device buffers; a
+small object layer (``Context``, ``Sketch``) frees handles automatically.
+
+The library must have been built (``python -m paper_1108_1320_amd.build``);
+``load()`` raises if it is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcmm.so")
+
+CMM_OK, CMM_EINVAL, CMM_ENOMEM, CMM_EHIP, CMM_EUNSUPPORTED, CMM_ESTATE = 0, -1, -2, -3, -4, -5
+CMM_F32, CMM_BF16, CMM_FP8_E4M3 = 0, 1, 2
+CMM_SUBTRACT_DIAG, CMM_ASYNC = 1, 2
+CMM_TOPK_ALL, CMM_TOPK_UPPER, CMM_TOPK_PER_COLUMN = 0, 1, 2
+DTYPES = {"f32": CMM_F32, "bf16": CMM_BF16, "fp8": CMM_FP8_E4M3}
+MODES = {"all": CMM_TOPK_ALL, "upper": CMM_TOPK_UPPER, "column": CMM_TOPK_PER_COLUMN}
+
+_lib = None
+
+_P = C.c_void_p
+_I64 = C.c_int64
+_I32 = C.c_int32
+_U32 = C.c_uint32
+_U64 = C.c_uint64
+
+_SIGS = {
+    "cmm_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
+    "cmm_ctx_set_stream": (C.c_int, [_P, _P]),
+    "cmm_ctx_destroy": (C.c_int, [_P]),
+    "cmm_strerror": (C.c_char_p, [C.c_int]),
+    "cmm_last_error": (C.c_char_p, [_P]),
+    "cmm_ctx_profile": (C.c_int, [_P, C.c_int]),
+    "cmm_ctx_profile_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(_I64)]),
+    "cmm_sketch_product": (C.c_int, [_P, _P, _P, _I64, _I64, _I32, _U64, C.POINTER(_P)]),
+    "cmm_sketch_product_ex": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P,
+                                        _I64, _I32, _U64, _P, _U32, C.POINTER(_P)]),
+    "cmm_sketch_product_tables": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P,
+                                            _I64, _I32, _P, _P, _P, _P, _U32, C.POINTER(_P)]),
+    "cmm_sketch_free": (C.c_int, [_P]),
+    "cmm_sketch_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64),
+                                  C.POINTER(_I64), C.POINTER(_I32)]),
+    "cmm_sketch_copy_c": (C.c_int, [_P, _P, _I64, _I32]),
+    "cmm_sketch_hash_params": (C.c_int, [_P, _P]),
+    "cmm_sketch_hashes": (C.c_int, [_P, _I32, _P, _P, _P, _P]),
+    "cmm_sketch_subtract_diagonal": (C.c_int, [_P, _P, _I64]),
+    "cmm_sketch_merge": (C.c_int, [_P, _P]),
+    "cmm_estimate": (C.c_int, [_P, _I64, _I64, C.POINTER(C.c_double)]),
+    "cmm_estimate_batch": (C.c_int, [_P, _P, _P, _I64, _P]),
+    "cmm_topk": (C.c_int, [_P, _I32, _I32, _P, _P, _P]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+class CmmError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str = ""):
+        super().__init__(f"{where}: {code} ({msg})")
+        self.code = code
+
+
+def load(path: str | None = None):
+    """Load libcmm.so (once).  Raises if the library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_1108_1320_amd.build`")
+    lib = C.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str, ctx=None):
+    if rc != CMM_OK:
+        lib = load()
+        msg = lib.cmm_last_error(ctx).decode() if ctx else lib.cmm_strerror(rc).decode()
+        raise CmmError(rc, where, msg)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _current_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ------------------------------------------------------------------ C names
+
+def cmm_ctx_create(device: int = 0, stream=None):
+    lib = load()
+    out = _P()
+    s = stream if stream is not None else _current_stream()
+    _check(lib.cmm_ctx_create(device, s, C.byref(out)), "cmm_ctx_create")
+    return out
+
+
+def cmm_ctx_destroy(ctx):
+    _check(load().cmm_ctx_destroy(ctx), "cmm_ctx_destroy")
+
+
+def cmm_ctx_set_stream(ctx, stream):
+    _check(load().cmm_ctx_set_stream(ctx, stream), "cmm_ctx_set_stream", ctx)
+
+
+def cmm_ctx_profile(ctx, enable: bool):
+    _check(load().cmm_ctx_profile(ctx, int(enable)), "cmm_ctx_profile", ctx)
+
+
+def cmm_ctx_profile_read(ctx, name: str):
+    ms = C.c_double(); n = _I64()
+    _check(load().cmm_ctx_profile_read(ctx, name.encode(), C.byref(ms), C.byref(n)),
+           "cmm_ctx_profile_read", ctx)
+    return ms.value, n.value
+
+
+def cmm_sketch_product(ctx, A, B, n: int, b: int, d: int, seed: int):
+    out = _P()
+    _check(load().cmm_sketch_product(ctx, _ptr(A), _ptr(B), n, b, d, seed, C.byref(out)),
+           "cmm_sketch_product", ctx)
+    return out
+
+
+def cmm_sketch_product_ex(ctx, A, lda, B, ldb, n1, m, n3, dtype, scaleA, scaleB, b, d, seed,
+                          hash_params=None, flags=0):
+    out = _P()
+    hp = None
+    if hash_params is not None:
+        hp = np.ascontiguousarray(hash_params, dtype=np.uint64)
+    _check(load().cmm_sketch_product_ex(
+        ctx, _ptr(A), lda, _ptr(B), ldb, n1, m, n3, dtype, _ptr(scaleA), _ptr(scaleB), b, d, seed,
+        None if hp is None else hp.ctypes.data_as(_P), flags, C.byref(out)),
+        "cmm_sketch_product_ex", ctx)
+    return out
+
+
+def cmm_sketch_product_tables(ctx, A, lda, B, ldb, n1, m, n3, dtype, scaleA, scaleB, b, d,
+                              h1, s1, h2, s2, flags=0):
+    out = _P()
+    h1 = np.ascontiguousarray(h1, dtype=np.int32); s1 = np.ascontiguousarray(s1, dtype=np.int8)
+    h2 = np.ascontiguousarray(h2, dtype=np.int32); s2 = np.ascontiguousarray(s2, dtype=np.int8)
+    _check(load().cmm_sketch_product_tables(
+        ctx, _ptr(A), lda, _ptr(B), ldb, n1, m, n3, dtype, _ptr(scaleA), _ptr(scaleB), b, d,
+        h1.ctypes.data_as(_P), s1.ctypes.data_as(_P), h2.ctypes.data_as(_P), s2.ctypes.data_as(_P),
+        flags, C.byref(out)), "cmm_sketch_product_tables", ctx)
+    return out
+
+
+def cmm_sketch_free(sk):
+    _check(load().cmm_sketch_free(sk), "cmm_sketch_free")
+
+
+def cmm_sketch_info(sk):
+    n1, m, n3, b = _I64(), _I64(), _I64(), _I64(); d = _I32()
+    _check(load().cmm_sketch_info(sk, C.byref(n1), C.byref(m), C.byref(n3), C.byref(b), C.byref(d)),
+           "cmm_sketch_info")
+    return n1.value, m.value, n3.value, b.value, d.value
+
+
+def cmm_sketch_copy_c(sk, out=None):
+    """c[d][b] as a float64 numpy array (or into a device tensor ``out``)."""
+    n1, m, n3, b, d = cmm_sketch_info(sk)
+    if out is not None:
+        _check(load().cmm_sketch_copy_c(sk, _ptr(out), d * b, 1), "cmm_sketch_copy_c")
+        return out
+    host = np.empty((d, b), dtype=np.float64)
+    _check(load().cmm_sketch_copy_c(sk, host.ctypes.data_as(_P), d * b, 0), "cmm_sketch_copy_c")
+    return host
+
+
+def cmm_sketch_hash_params(sk):
+    n1, m, n3, b, d = cmm_sketch_info(sk)
+    out = np.empty((d, 4, 2), dtype=np.uint64)
+    _check(load().cmm_sketch_hash_params(sk, out.ctypes.data_as(_P)), "cmm_sketch_hash_params")
+    return out
+
+
+def cmm_sketch_hashes(sk, t: int):
+    n1, m, n3, b, d = cmm_sketch_info(sk)
+    h1 = np.empty(n1, np.int32); s1 = np.empty(n1, np.int8)
+    h2 = np.empty(n3, np.int32); s2 = np.empty(n3, np.int8)
+    _check(load().cmm_sketch_hashes(sk, t, h1.ctypes.data_as(_P), s1.ctypes.data_as(_P),
+                                    h2.ctypes.data_as(_P), s2.ctypes.data_as(_P)),
+           "cmm_sketch_hashes")
+    return h1, s1, h2, s2
+
+
+def cmm_sketch_subtract_diagonal(sk, diag):
+    _check(load().cmm_sketch_subtract_diagonal(sk, _ptr(diag), diag.numel()),
+           "cmm_sketch_subtract_diagonal")
+
+
+def cmm_sketch_merge(dst, src):
+    _check(load().cmm_sketch_merge(dst, src), "cmm_sketch_merge")
+
+
+def cmm_estimate(sk, i: int, j: int) -> float:
+    v = C.c_double()
+    _check(load().cmm_estimate(sk, i, j, C.byref(v)), "cmm_estimate")
+    return v.value
+
+
+def cmm_estimate_batch(sk, i, j, out):
+    _check(load().cmm_estimate_batch(sk, _ptr(i), _ptr(j), i.numel(), _ptr(out)),
+           "cmm_estimate_batch")
+    return out
+
+
+def cmm_topk(sk, K: int, mode: int):
+    n1, m, n3, b, d = cmm_sketch_info(sk)
+    cnt = K * n3 if mode == CMM_TOPK_PER_COLUMN else K
+    oi = np.empty(cnt, np.int64); oj = np.empty(cnt, np.int64); ov = np.empty(cnt, np.float32)
+    _check(load().cmm_topk(sk, K, mode, oi.ctypes.data_as(_P), oj.ctypes.data_as(_P),
+                           ov.ctypes.data_as(_P)), "cmm_topk")
+    return oi, oj, ov
+
+
+# ------------------------------------------------------------- object layer
+
+class Context:
+    """A cmm context on one device, ordered on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.handle = cmm_ctx_create(device, stream)
+
+    def close(self):
+        if self.handle:
+            cmm_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def profile(self, enable: bool):
+        cmm_ctx_profile(self.handle, enable)
+
+    def profile_read(self, name: str):
+        return cmm_ctx_profile_read(self.handle, name)
+
+
+class Sketch:
+    """Owning wrapper of a cmm_sketch handle."""
+
+    def __init__(self, handle, ctx: Context):
+        self.handle = handle
+        self.ctx = ctx   # keeps the context alive
+
+    def free(self):
+        if self.handle:
+            cmm_sketch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self):
+        return cmm_sketch_info(self.handle)
+
+    def c(self):
+        return cmm_sketch_copy_c(self.handle)
+
+    def hash_params(self):
+        return cmm_sketch_hash_params(self.handle)
+
+    def hashes(self, t):
+        return cmm_sketch_hashes(self.handle, t)
+
+    def estimate(self, i, j):
+        return cmm_estimate(self.handle, i, j)
+
+    def estimate_batch(self, i, j):
+        import torch
+        out = torch.empty(i.numel(), dtype=torch.float32, device=i.device)
+        return cmm_estimate_batch(self.handle, i, j, out)
+
+    def topk(self, K, mode="all"):
+        return cmm_topk(self.handle, K, MODES[mode] if isinstance(mode, str) else mode)
+
+    def subtract_diagonal(self, diag):
+        cmm_sketch_subtract_diagonal(self.handle, diag)
+
+    def merge(self, other: "Sketch"):
+        cmm_sketch_merge(self.handle, other.handle)
+
+
+def sketch_product(ctx: Context, At, B, b: int, d: int, seed: int = 0, dtype: str = "f32",
+                   scaleA=None, scaleB=None, hash_params=None, subtract_diag: bool = False,
+                   n1: int | None = None, n3: int | None = None, m: int | None = None,
+                   asynchronous: bool = False) -> Sketch:
+    """Sketch of AB from the k-major device arrays At (m x lda, At[k, i] =
+    A[i, k]) and B (m x ldb).  Returns a Sketch."""
+    m_ = m if m is not None else At.shape[0]
+    n1_ = n1 if n1 is not None else At.shape[1]
+    n3_ = n3 if n3 is not None else B.shape[1]
+    flags = (CMM_SUBTRACT_DIAG if subtract_diag else 0) | (CMM_ASYNC if asynchronous else 0)
+    h = cmm_sketch_product_ex(ctx.handle, At, At.stride(0), B, B.stride(0), n1_, m_, n3_,
+                              DTYPES[dtype], scaleA, scaleB, b, d, seed, hash_params, flags)
+    return Sketch(h, ctx)
+
+
+def sketch_product_tables(ctx: Context, At, B, b, h1, s1, h2, s2, dtype="f32") -> Sketch:
+    d = np.asarray(h1).shape[0]
+    h = cmm_sketch_product_tables(ctx.handle, At, At.stride(0), B, B.stride(0), At.shape[1],
+                                  At.shape[0], B.shape[1], DTYPES[dtype], None, None, b, d,
+                                  h1, s1, h2, s2)
+    return Sketch(h, ctx)

@@ -1,0 +1,117 @@
+// Internal declarations of the cmm HIP library (not part of the C ABI).
+//
+// Data layout in HBM for one product AB (A n1 x m column-major, B m x n3
+// row-major; "side" 0 hashes the rows i of A with (h1, s1), side 1 the
+// columns j of B with (h2, s2)):
+//
+//   hs[side][t][x]        int32  (h(x) << 1) | (s(x) == -1)
+//   cnt[side][t][u]       int32  members of bucket u (u < b)
+//   pos[side][t][u]       int32  layout position of non-empty bucket u, -1 if empty
+//   ent[side][t][p]       uint32 bucket id at layout position p (bit 31 = padding)
+//   tab[side][t][p]       uint32 first member | sign << 31 | more-members << 30
+//   SA[side][t][k][p]     float  count sketch of column k (side 0) / row k (side 1)
+//   Ppart[t][ks][f1][f2]  double2 partial spectral sums of one k-split
+//   c64[t][u], c32[t][u]  the sketch
+//
+// Layout positions: the fused FFT kernel works on C-point rows with T = C/16
+// threads; the thread that owns slot r (r = u mod C) is r mod T, and the
+// wave that owns it is (u mod T) / G with G = min(T, 64).  Each of the
+// W = T / G waves gets one segment of Lcap positions holding the non-empty
+// buckets it owns (increasing u), padded to a multiple of 64 (lseg[side][t]).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define CMM_P61 0x1FFFFFFFFFFFFFFFull
+#define CMM_PAD_ENT 0x80000000u
+#define CMM_PAD_TAB 0xFFFFFFFFu
+#define CMM_TAB_NEG 0x80000000u
+#define CMM_TAB_MORE 0x40000000u
+#define CMM_TAB_IDX 0x3FFFFFFFu
+
+namespace cmm {
+
+constexpr int kMaxLog2C = 12;          // FFT row length C <= 4096
+constexpr int kTopkCap = 4096;         // candidates sorted by the final top-K pass
+
+struct SideDesc {
+  const void* X;        // stored operand (k-major rows of length n)
+  int64_t ld;           // row stride in elements
+  const float* scale;   // per-element-position scale (fp8) or nullptr
+  int n;                // hashed dimension (n1 or n3)
+  int32_t* hs;          // [d][n]
+  int32_t* cnt;         // [d][b]
+  int32_t* pos;         // [d][b]
+  uint32_t* ent;        // [d][Lrow]
+  uint32_t* tab;        // [d][Lrow]
+  int32_t* cntp;        // [d][Lrow]
+  int32_t* moff;        // [d][Lrow]
+  int32_t* fill;        // [d][Lrow]
+  int32_t* perm;        // [d][n]
+  int32_t* segcount;    // [d][W]
+  int32_t* lseg;        // [d]
+  float* SA;            // [d][m][Lrow]
+  int Lcap;             // positions per segment
+  int Lrow;             // W * Lcap
+};
+
+struct Geometry {
+  int64_t b;
+  int log2b;
+  int d;
+  int m;
+  int log2c;            // FFT row length C = 1 << log2c
+  int T;                // threads of the FFT kernel = C / 16
+  int G;                // lanes per segment class group = min(T, 64)
+  int W;                // segments = T / G
+  int R;                // rows of the four-step split = b / C
+  int rows;             // computed rows (R/2 + 1, or 1 when R == 1)
+  int KS;               // k-splits of the FFT kernel
+};
+
+// ---- kernel launchers (stream-ordered, return hipError_t) ----
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
+hipError_t launch_twiddles(double2* tw64, float2* tw32, int64_t b, hipStream_t s);
+hipError_t launch_hash(const uint64_t* params_dev, int side, const Geometry& g, SideDesc& sd,
+                       hipStream_t s);
+hipError_t launch_count(const Geometry& g, SideDesc& sd, hipStream_t s);
+hipError_t launch_layout(const Geometry& g, SideDesc& sd, int32_t* overflow, hipStream_t s);
+hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStream_t s);
+hipError_t launch_fft_mac(const Geometry& g, const SideDesc& a, const SideDesc& bside,
+                          const float2* tw32, double2* Ppart, hipStream_t s);
+hipError_t launch_ifft(const Geometry& g, const double2* Ppart, double2* work0, double2* work1,
+                       const double2* tw64, double* c64, hipStream_t s);
+hipError_t launch_diag(int dtype, const SideDesc& a, const SideDesc& bside, int m, int n,
+                       double* partial, int kchunks, double* diag, hipStream_t s);
+hipError_t launch_sub_diag(const Geometry& g, const int32_t* hs1, const int32_t* hs2, int n1,
+                           int n3, const double* diag, int len, double* c64, hipStream_t s);
+hipError_t launch_to_f32(const double* c64, float* c32, int64_t count, hipStream_t s);
+hipError_t launch_add_f64(double* dst, const double* src, int64_t count, hipStream_t s);
+
+struct DecodeDesc {
+  const int32_t* hs1;   // [d][n1]
+  const int32_t* hs2;   // [d][n3]
+  const float* c32;     // [d][b]
+  int n1, n3, d;
+  uint32_t mask;        // b - 1
+  int64_t b;
+};
+
+struct TopkCand {
+  uint32_t key;         // float bits of |estimate|
+  int32_t i, j;
+  float val;
+};
+
+hipError_t launch_estimate(const DecodeDesc& dd, const int64_t* qi, const int64_t* qj, int64_t q,
+                           float* out, hipStream_t s);
+hipError_t launch_topk_hist(const DecodeDesc& dd, int mode, uint32_t prefix, int prefix_shift,
+                            int digit_shift, uint32_t digit_mask, uint32_t* hist, hipStream_t s);
+hipError_t launch_topk_collect(const DecodeDesc& dd, int mode, uint32_t thresh, TopkCand* cand,
+                               uint32_t* count, int cap, hipStream_t s);
+hipError_t launch_topk_final(const TopkCand* cand, const uint32_t* count, int cap, int K, int n3,
+                             int64_t* oi, int64_t* oj, float* ov, hipStream_t s);
+hipError_t launch_topk_column(const DecodeDesc& dd, int K, int64_t* oi, float* ov, hipStream_t s);
+
+}  // namespace cmm

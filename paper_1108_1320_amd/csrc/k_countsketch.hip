@@ -1,0 +1,141 @@
+// COUNT SKETCH of every column a_k of A and row b_k of B (the polynomials
+// p_{a_k}^{h1,s1} and p_{b_k}^{h2,s2} of Section 2.2 / Figure 1), for all d
+// repetitions from one read of each input row.
+//
+// The stored operands are k-major (Section 2.2's single-pass order), so the
+// vector to sketch for a given k is one contiguous row of n elements.  A
+// block stages that row in LDS (dequantising bf16 / fp8 and applying the
+// per-position scale), then, for every repetition, writes the row's sketch
+// in the bucket layout of the FFT kernel: position p holds the signed sum of
+// the row entries of the bucket placed there.  Members of a bucket are summed
+// in increasing index order, so the result does not depend on scheduling.
+// The kernel streams its input once and writes d compact sketches; it is
+// bound by HBM bandwidth.
+#include "cmm_internal.h"
+
+namespace cmm {
+
+__device__ __forceinline__ float e4m3fn_to_f32(uint32_t v) {
+  uint32_t sign = (v & 0x80u) << 24;
+  uint32_t e = (v >> 3) & 0xFu, mnt = v & 7u;
+  float mag;
+  if (e == 0) mag = (float)mnt * 0x1p-9f;
+  else if (e == 15 && mnt == 7) mag = __uint_as_float(0x7FC00000u);
+  else mag = __uint_as_float(((e + 120u) << 23) | (mnt << 20));
+  return __uint_as_float(__float_as_uint(mag) | sign);
+}
+
+template <int DT> struct Elem;
+template <> struct Elem<0> {      // f32
+  typedef float S; typedef float4 V4;
+  static __device__ __forceinline__ float one(S s) { return s; }
+  static __device__ __forceinline__ void four(V4 v, float* o) { o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
+};
+template <> struct Elem<1> {      // bf16 bits
+  typedef uint16_t S; typedef uint2 V4;
+  static __device__ __forceinline__ float one(S s) { return __uint_as_float((uint32_t)s << 16); }
+  static __device__ __forceinline__ void four(V4 v, float* o) {
+    o[0] = __uint_as_float(v.x << 16); o[1] = __uint_as_float(v.x & 0xFFFF0000u);
+    o[2] = __uint_as_float(v.y << 16); o[3] = __uint_as_float(v.y & 0xFFFF0000u);
+  }
+};
+template <> struct Elem<2> {      // fp8 e4m3fn bits
+  typedef uint8_t S; typedef uint32_t V4;
+  static __device__ __forceinline__ float one(S s) { return e4m3fn_to_f32(s); }
+  static __device__ __forceinline__ void four(V4 v, float* o) {
+    o[0] = e4m3fn_to_f32(v & 0xFF); o[1] = e4m3fn_to_f32((v >> 8) & 0xFF);
+    o[2] = e4m3fn_to_f32((v >> 16) & 0xFF); o[3] = e4m3fn_to_f32(v >> 24);
+  }
+};
+
+// grid.x = k-blocks; block = 256 threads; dynamic LDS = n floats.
+template <int DT, bool VEC>
+__global__ __launch_bounds__(256) void k_countsketch(SideDesc sd, int d, int m, int W, int kblock) {
+  extern __shared__ float row[];
+  typedef Elem<DT> E;
+  const int tid = threadIdx.x;
+  const int n = sd.n;
+  const int k0 = blockIdx.x * kblock;
+  const int k1 = min(m, k0 + kblock);
+  const typename E::S* X = (const typename E::S*)sd.X;
+  for (int k = k0; k < k1; ++k) {
+    const typename E::S* xr = X + (int64_t)k * sd.ld;
+    if (VEC) {
+      const typename E::V4* xv = (const typename E::V4*)xr;
+      const int n4 = n >> 2;
+      for (int q = tid; q < n4; q += 256) {
+        float o[4];
+        E::four(xv[q], o);
+        if (sd.scale) {
+          const float4 sc = ((const float4*)sd.scale)[q];
+          o[0] *= sc.x; o[1] *= sc.y; o[2] *= sc.z; o[3] *= sc.w;
+        }
+        *(float4*)&row[4 * q] = make_float4(o[0], o[1], o[2], o[3]);
+      }
+      for (int x = 4 * n4 + tid; x < n; x += 256)
+        row[x] = E::one(xr[x]) * (sd.scale ? sd.scale[x] : 1.0f);
+    } else {
+      for (int x = tid; x < n; x += 256)
+        row[x] = E::one(xr[x]) * (sd.scale ? sd.scale[x] : 1.0f);
+    }
+    __syncthreads();
+    for (int t = 0; t < d; ++t) {
+      const int L = sd.lseg[t];
+      const int total = W * L;
+      const uint32_t* tab = sd.tab + (int64_t)t * sd.Lrow;
+      float* out = sd.SA + ((int64_t)t * m + k) * sd.Lrow;
+      for (int idx = tid; idx < total; idx += 256) {
+        const int w = idx / L;
+        const int p = w * sd.Lcap + (idx - w * L);
+        const uint32_t e = tab[p];
+        float v = 0.0f;
+        if (e != CMM_PAD_TAB) {
+          v = row[e & CMM_TAB_IDX];
+          if (e & CMM_TAB_NEG) v = -v;
+          if (e & CMM_TAB_MORE) {
+            const int64_t tp = (int64_t)t * sd.Lrow + p;
+            const int c = sd.cntp[tp];
+            const int32_t* mem = sd.perm + (int64_t)t * n + sd.moff[tp];
+            const int32_t* hs = sd.hs + (int64_t)t * n;
+            for (int a = 1; a < c; ++a) {
+              const int x = mem[a];
+              const float y = row[x];
+              v += (hs[x] & 1) ? -y : y;
+            }
+          }
+        }
+        out[p] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStream_t s) {
+  const int esz = dtype == 0 ? 4 : (dtype == 1 ? 2 : 1);
+  const bool vec = (sd.n % 4 == 0) && (sd.ld % 4 == 0) &&
+                   ((uintptr_t)sd.X % (4 * esz) == 0) &&
+                   (sd.scale == nullptr || (uintptr_t)sd.scale % 16 == 0);
+  // aim for ~2048 blocks
+  int kblock = (int)((int64_t)g.m / 2048);
+  if (kblock < 1) kblock = 1;
+  const int blocks = (g.m + kblock - 1) / kblock;
+  const size_t lds = (size_t)sd.n * sizeof(float);
+#define CMM_CS(DTV, VV)                                                                     \
+  do {                                                                                      \
+    if (lds > 64 * 1024) {                                                                  \
+      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_countsketch<DTV, VV>), \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      if (e_ != hipSuccess) return e_;                                                      \
+    }                                                                                       \
+    hipLaunchKernelGGL((k_countsketch<DTV, VV>), dim3(blocks), dim3(256), lds, s, sd, g.d, g.m, \
+                       g.W, kblock);                                                        \
+  } while (0)
+  if (dtype == 0) { if (vec) CMM_CS(0, true); else CMM_CS(0, false); }
+  else if (dtype == 1) { if (vec) CMM_CS(1, true); else CMM_CS(1, false); }
+  else { if (vec) CMM_CS(2, true); else CMM_CS(2, false); }
+#undef CMM_CS
+  return hipGetLastError();
+}
+
+}  // namespace cmm

@@ -1,0 +1,294 @@
+// Decoding (Figure 1, DECOMPRESS): X_t = s1_t(i) s2_t(j) c_t[(h1_t(i) +
+// h2_t(j)) mod b], estimate = median over the d repetitions (Section 3.3),
+// and selection of the estimates of largest magnitude without storing the
+// n1-by-n3 estimate matrix (the product stays implicit, Section 2.2).
+//
+// Global top-K works on the 32-bit key |estimate| (float bits are ordered
+// like the values for non-negative floats) in passes that re-decode the
+// candidate domain: a histogram of the key's top 12 bits locates the bin of
+// the K-th largest key, further 12- and 7-bit digit passes refine it if the
+// bin is crowded, one pass collects every candidate at or above the
+// threshold, and a single block sorts them by (key desc, i*n3+j asc).
+#include "cmm_internal.h"
+
+namespace cmm {
+
+template <int D>
+__device__ __forceinline__ float estimate(const DecodeDesc& dd, const int32_t* a1, const int32_t* a2,
+                                          int dr) {
+  // a1[t] = hs1[t][i], a2[t] = hs2[t][j]
+  if constexpr (D > 0) {
+    float x[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      const uint32_t u = (uint32_t)((a1[t] >> 1) + (a2[t] >> 1)) & dd.mask;
+      const float v = dd.c32[(int64_t)t * dd.b + u];
+      x[t] = ((a1[t] ^ a2[t]) & 1) ? -v : v;
+    }
+    // odd-even transposition sort, D rounds
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+#pragma unroll
+      for (int q = (r & 1); q + 1 < D; q += 2) {
+        const float lo = fminf(x[q], x[q + 1]), hi = fmaxf(x[q], x[q + 1]);
+        x[q] = lo; x[q + 1] = hi;
+      }
+    }
+    if constexpr (D & 1) return x[(D - 1) / 2];
+    else return 0.5f * (x[D / 2 - 1] + x[D / 2]);
+  } else {
+    float x[64];
+    for (int t = 0; t < dr; ++t) {
+      const uint32_t u = (uint32_t)((a1[t] >> 1) + (a2[t] >> 1)) & dd.mask;
+      const float v = dd.c32[(int64_t)t * dd.b + u];
+      const float y = ((a1[t] ^ a2[t]) & 1) ? -v : v;
+      int q = t - 1;
+      while (q >= 0 && x[q] > y) { x[q + 1] = x[q]; --q; }
+      x[q + 1] = y;
+    }
+    return (dr & 1) ? x[(dr - 1) / 2] : 0.5f * (x[dr / 2 - 1] + x[dr / 2]);
+  }
+}
+
+template <int D> struct HashVec {
+  int32_t v[D > 0 ? D : 64];
+};
+
+template <int D>
+__device__ __forceinline__ void load_hash(HashVec<D>& h, const int32_t* hs, int n, int x, int dr) {
+  if constexpr (D > 0) {
+#pragma unroll
+    for (int t = 0; t < D; ++t) h.v[t] = hs[(int64_t)t * n + x];
+  } else {
+    for (int t = 0; t < dr; ++t) h.v[t] = hs[(int64_t)t * n + x];
+  }
+}
+
+// ---------------------------------------------------------------- batch
+
+template <int D>
+__global__ void k_estimate(DecodeDesc dd, const int64_t* __restrict__ qi,
+                           const int64_t* __restrict__ qj, int64_t q, float* __restrict__ out) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < q;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = qi[idx], j = qj[idx];
+    if (i < 0 || j < 0 || i >= dd.n1 || j >= dd.n3) { out[idx] = __uint_as_float(0x7FC00000u); continue; }
+    HashVec<D> h1, h2;
+    load_hash<D>(h1, dd.hs1, dd.n1, (int)i, dd.d);
+    load_hash<D>(h2, dd.hs2, dd.n3, (int)j, dd.d);
+    out[idx] = estimate<D>(dd, h1.v, h2.v, dd.d);
+  }
+}
+
+// ------------------------------------------------------------- top-K passes
+// Tile: 16 rows i (uniform in the block) x 256 columns j (one per thread).
+constexpr int kTI = 16;
+
+__device__ __forceinline__ bool in_domain(int mode, int i, int j, int n1, int n3) {
+  return i < n1 && j < n3 && (mode != 1 || i < j);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_topk_hist(DecodeDesc dd, int mode, uint32_t pmask,
+                                                   uint32_t prefix, int dshift, uint32_t dmask,
+                                                   uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[4096];
+  const int tid = threadIdx.x;
+  const int j = blockIdx.x * 256 + tid;
+  const int i0 = blockIdx.y * kTI;
+  if (mode == 1 && i0 >= (int)(blockIdx.x * 256 + 255)) return;   // tile below the diagonal
+  for (int q = tid; q < 4096; q += 256) h[q] = 0;
+  __syncthreads();
+  if (j < dd.n3) {
+    HashVec<D> h2;
+    load_hash<D>(h2, dd.hs2, dd.n3, j, dd.d);
+    for (int ii = 0; ii < kTI; ++ii) {
+      const int i = i0 + ii;
+      if (!in_domain(mode, i, j, dd.n1, dd.n3)) continue;
+      HashVec<D> h1;
+      load_hash<D>(h1, dd.hs1, dd.n1, i, dd.d);
+      const uint32_t key = __float_as_uint(fabsf(estimate<D>(dd, h1.v, h2.v, dd.d)));
+      if ((key & pmask) == prefix) atomicAdd(&h[(key >> dshift) & dmask], 1u);
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < 4096; q += 256)
+    if (h[q]) atomicAdd(&hist[q], h[q]);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_topk_collect(DecodeDesc dd, int mode, uint32_t thresh,
+                                                      TopkCand* __restrict__ cand,
+                                                      uint32_t* __restrict__ count, int cap) {
+  const int tid = threadIdx.x;
+  const int j = blockIdx.x * 256 + tid;
+  const int i0 = blockIdx.y * kTI;
+  if (mode == 1 && i0 >= (int)(blockIdx.x * 256 + 255)) return;
+  if (j >= dd.n3) return;
+  HashVec<D> h2;
+  load_hash<D>(h2, dd.hs2, dd.n3, j, dd.d);
+  for (int ii = 0; ii < kTI; ++ii) {
+    const int i = i0 + ii;
+    if (!in_domain(mode, i, j, dd.n1, dd.n3)) continue;
+    HashVec<D> h1;
+    load_hash<D>(h1, dd.hs1, dd.n1, i, dd.d);
+    const float est = estimate<D>(dd, h1.v, h2.v, dd.d);
+    const uint32_t key = __float_as_uint(fabsf(est));
+    if (key >= thresh) {
+      const uint32_t slot = atomicAdd(count, 1u);
+      if (slot < (uint32_t)cap) {
+        TopkCand c; c.key = key; c.i = i; c.j = j; c.val = est;
+        cand[slot] = c;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ bool later(const TopkCand& a, const TopkCand& b, int n3) {
+  // true if a sorts after b: smaller key, or equal key and larger i*n3+j
+  if (a.key != b.key) return a.key < b.key;
+  return (int64_t)a.i * n3 + a.j > (int64_t)b.i * n3 + b.j;
+}
+
+__global__ __launch_bounds__(1024) void k_topk_final(const TopkCand* __restrict__ cand,
+                                                     const uint32_t* __restrict__ count, int cap,
+                                                     int K, int n3, int64_t* __restrict__ oi,
+                                                     int64_t* __restrict__ oj,
+                                                     float* __restrict__ ov) {
+  __shared__ TopkCand s[kTopkCap];
+  const int tid = threadIdx.x;
+  const uint32_t cnt = *count;
+  const int n = (int)(cnt < (uint32_t)cap ? cnt : (uint32_t)cap);
+  int N2 = 1;
+  while (N2 < n) N2 <<= 1;
+  for (int q = tid; q < N2; q += 1024) {
+    if (q < n) s[q] = cand[q];
+    else { TopkCand z; z.key = 0; z.i = 0x7FFFFFFF; z.j = 0x7FFFFFFF; z.val = 0.f; s[q] = z; }
+  }
+  for (int size = 2; size <= N2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int q = tid; q < N2; q += 1024) {
+        const int l = q ^ stride;
+        if (l > q) {
+          const TopkCand a = s[q], b = s[l];
+          const bool up = (q & size) == 0;
+          if (up ? later(a, b, n3) : later(b, a, n3)) { s[q] = b; s[l] = a; }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < K; r += 1024) {
+    if (r < n) { oi[r] = s[r].i; oj[r] = s[r].j; ov[r] = s[r].val; }
+    else { oi[r] = -1; oj[r] = -1; ov[r] = 0.f; }
+  }
+}
+
+// ---------------------------------------------------------------- per column
+
+template <int D>
+__global__ __launch_bounds__(256) void k_topk_column(DecodeDesc dd, int K, int64_t* __restrict__ oi,
+                                                     float* __restrict__ ov) {
+  extern __shared__ uint32_t keys[];
+  __shared__ unsigned long long wbest[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int j = blockIdx.x;
+  HashVec<D> h2;
+  load_hash<D>(h2, dd.hs2, dd.n3, j, dd.d);
+  for (int i = tid; i < dd.n1; i += 256) {
+    HashVec<D> h1;
+    load_hash<D>(h1, dd.hs1, dd.n1, i, dd.d);
+    keys[i] = __float_as_uint(fabsf(estimate<D>(dd, h1.v, h2.v, dd.d)));
+  }
+  __syncthreads();
+  unsigned long long last = ~0ull;
+  for (int r = 0; r < K; ++r) {
+    // packed (key, ~i): larger is better; pick the best strictly below `last`
+    unsigned long long best = 0ull;
+    for (int i = tid; i < dd.n1; i += 256) {
+      const unsigned long long p = ((unsigned long long)keys[i] << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)i);
+      if (p < last && p > best) best = p;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(best, off, 64);
+      best = o > best ? o : best;
+    }
+    if (lane == 0) wbest[wv] = best;
+    __syncthreads();
+    best = wbest[0];
+    for (int q = 1; q < 4; ++q) best = wbest[q] > best ? wbest[q] : best;
+    __syncthreads();
+    last = best;
+    if (tid == 0) {
+      const int i = (int)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFull));
+      HashVec<D> h1;
+      load_hash<D>(h1, dd.hs1, dd.n1, i, dd.d);
+      oi[(int64_t)j * K + r] = i;
+      ov[(int64_t)j * K + r] = estimate<D>(dd, h1.v, h2.v, dd.d);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+#define CMM_DISPATCH_D(d, MACRO)                                                   \
+  switch (d) {                                                                     \
+    case 1: MACRO(1); break;  case 2: MACRO(2); break;  case 3: MACRO(3); break;   \
+    case 4: MACRO(4); break;  case 5: MACRO(5); break;  case 6: MACRO(6); break;   \
+    case 7: MACRO(7); break;  case 8: MACRO(8); break;  case 9: MACRO(9); break;   \
+    case 10: MACRO(10); break; case 11: MACRO(11); break; case 12: MACRO(12); break; \
+    case 13: MACRO(13); break; case 14: MACRO(14); break; case 15: MACRO(15); break; \
+    default: MACRO(0); break;                                                      \
+  }
+
+static inline unsigned grid1(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 16384) g = 16384;
+  return (unsigned)g;
+}
+
+hipError_t launch_estimate(const DecodeDesc& dd, const int64_t* qi, const int64_t* qj, int64_t q,
+                           float* out, hipStream_t s) {
+  if (q <= 0) return hipSuccess;
+#define CMM_EST(DV) hipLaunchKernelGGL(k_estimate<DV>, dim3(grid1(q)), dim3(256), 0, s, dd, qi, qj, q, out)
+  CMM_DISPATCH_D(dd.d, CMM_EST)
+#undef CMM_EST
+  return hipGetLastError();
+}
+
+hipError_t launch_topk_hist(const DecodeDesc& dd, int mode, uint32_t prefix, int prefix_shift,
+                            int digit_shift, uint32_t digit_mask, uint32_t* hist, hipStream_t s) {
+  const uint32_t pmask = prefix_shift >= 32 ? 0u : ~((1u << prefix_shift) - 1u);
+  dim3 grid((dd.n3 + 255) / 256, (dd.n1 + kTI - 1) / kTI);
+#define CMM_H(DV) hipLaunchKernelGGL(k_topk_hist<DV>, grid, dim3(256), 0, s, dd, mode, pmask, prefix & pmask, digit_shift, digit_mask, hist)
+  CMM_DISPATCH_D(dd.d, CMM_H)
+#undef CMM_H
+  return hipGetLastError();
+}
+
+hipError_t launch_topk_collect(const DecodeDesc& dd, int mode, uint32_t thresh, TopkCand* cand,
+                               uint32_t* count, int cap, hipStream_t s) {
+  dim3 grid((dd.n3 + 255) / 256, (dd.n1 + kTI - 1) / kTI);
+#define CMM_C(DV) hipLaunchKernelGGL(k_topk_collect<DV>, grid, dim3(256), 0, s, dd, mode, thresh, cand, count, cap)
+  CMM_DISPATCH_D(dd.d, CMM_C)
+#undef CMM_C
+  return hipGetLastError();
+}
+
+hipError_t launch_topk_final(const TopkCand* cand, const uint32_t* count, int cap, int K, int n3,
+                             int64_t* oi, int64_t* oj, float* ov, hipStream_t s) {
+  hipLaunchKernelGGL(k_topk_final, dim3(1), dim3(1024), 0, s, cand, count, cap, K, n3, oi, oj, ov);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk_column(const DecodeDesc& dd, int K, int64_t* oi, float* ov, hipStream_t s) {
+  const size_t lds = (size_t)dd.n1 * sizeof(uint32_t);
+#define CMM_K(DV) hipLaunchKernelGGL(k_topk_column<DV>, dim3(dd.n3), dim3(256), lds, s, dd, K, oi, ov)
+  CMM_DISPATCH_D(dd.d, CMM_K)
+#undef CMM_K
+  return hipGetLastError();
+}
+
+}  // namespace cmm

@@ -1,0 +1,238 @@
+// Inverse transform of the accumulated spectrum (Figure 1: p[t] :=
+// FFT^-1(p[t])), the diagonal correction of Section 3.2, and small linear
+// helpers.  Everything here is float64.
+//
+// The FFT kernel leaves, per k-split, rows f1 in [0, R/2] of the spectrum
+// (frequency f = f1 + R f2).  The reduction sums the k-splits in a fixed
+// order and rebuilds the full length-b spectrum from Hermitian symmetry:
+// for f1 > R/2, P[f1 + R f2] = conj P[(R - f1) + R (C - 1 - f2)].  The
+// inverse DFT then runs as global-memory Stockham passes (radix 16 with one
+// smaller first pass), and c_t[u] = Re(.)/b.
+#include "cmm_internal.h"
+#include "cmm_dft.h"
+
+namespace cmm {
+
+// Psum[t][f1][f2] = sum over ks of Ppart[t][ks][f1][f2]
+__global__ void k_reduce_splits(const double2* __restrict__ Ppart, int KS, int rows, int C,
+                                int d, double2* __restrict__ Psum) {
+  const int64_t per_t = (int64_t)rows * C;
+  const int64_t total = (int64_t)d * per_t;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(idx / per_t);
+    const int64_t rest = idx - (int64_t)t * per_t;
+    const double2* src = Ppart + (int64_t)t * KS * per_t + rest;
+    double sx = 0.0, sy = 0.0;
+    for (int ks = 0; ks < KS; ++ks) {
+      const double2 v = src[(int64_t)ks * per_t];
+      sx += v.x; sy += v.y;
+    }
+    Psum[idx] = make_double2(sx, sy);
+  }
+}
+
+__global__ void k_assemble(const double2* __restrict__ Psum, int R, int rows, int C, int64_t b,
+                           int d, double2* __restrict__ P) {
+  const int64_t total = (int64_t)d * b;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(idx / b);
+    const int64_t f = idx - (int64_t)t * b;
+    int f1 = (int)(f & (R - 1));
+    int64_t f2 = f / R;
+    bool cj = false;
+    if (R > 1 && 2 * f1 > R) { f1 = R - f1; f2 = C - 1 - f2; cj = true; }
+    double2 v = Psum[((int64_t)t * rows + f1) * C + f2];
+    if (cj) v.y = -v.y;
+    P[idx] = v;
+  }
+}
+
+// One inverse Stockham pass of radix RS over every repetition:
+// out[(jb/Ns) Ns RS + jb mod Ns + r Ns] = IDFT_RS( in[jb + r b/RS] conj(w) ).
+template <int RS>
+__global__ void k_ifft_pass(const double2* __restrict__ in, double2* __restrict__ out,
+                            const double2* __restrict__ tw, int64_t b, int d, int64_t Ns) {
+  const int64_t nb = b / RS;
+  const int64_t total = (int64_t)d * nb;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(idx / nb);
+    const int64_t jb = idx - (int64_t)t * nb;
+    const double2* src = in + (int64_t)t * b;
+    double2* dst = out + (int64_t)t * b;
+    const int64_t jm = jb % Ns;
+    const int64_t step = b / (Ns * RS);
+    double2 x[RS];
+#pragma unroll
+    for (int r = 0; r < RS; ++r) {
+      // inverse = conj(DFT(conj(x) * w)), with twiddle w^(jm r)
+      double2 v = cconj(src[jb + (int64_t)r * nb]);
+      if (r > 0 && jm > 0) v = cmul(v, tw[(jm * r * step) & (b - 1)]);
+      x[r] = v;
+    }
+    dft<RS>(x);
+    const int64_t base = (jb / Ns) * Ns * RS + jm;
+#pragma unroll
+    for (int r = 0; r < RS; ++r) dst[base + (int64_t)r * Ns] = cconj(x[r]);
+  }
+}
+
+__global__ void k_real_part(const double2* __restrict__ z, double inv_b, int64_t count,
+                            double* __restrict__ c) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    c[i] = z[i].x * inv_b;
+}
+
+static inline unsigned grid_for(int64_t n, int64_t cap = 16384) {
+  int64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+hipError_t launch_ifft(const Geometry& g, const double2* Ppart, double2* work0, double2* work1,
+                       const double2* tw64, double* c64, hipStream_t s) {
+  const int C = 1 << g.log2c;
+  const int64_t nsum = (int64_t)g.d * g.rows * C;
+  // Psum lives in work1 (size d*b >= d*rows*C), the assembled spectrum in work0
+  hipLaunchKernelGGL(k_reduce_splits, dim3(grid_for(nsum)), dim3(256), 0, s, Ppart, g.KS,
+                     g.rows, C, g.d, work1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_assemble, dim3(grid_for((int64_t)g.d * g.b)), dim3(256), 0, s, work1,
+                     g.R, g.rows, C, g.b, g.d, work0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  double2* src = work0;
+  double2* dst = work1;
+  int64_t Ns = 1;
+  const int rem = g.log2b % 4;
+  int passes = g.log2b / 4 + (rem ? 1 : 0);
+  for (int p = 0; p < passes; ++p) {
+    const int rs = (p == 0 && rem) ? (1 << rem) : 16;
+    const int64_t nthreads = (int64_t)g.d * (g.b / rs);
+    switch (rs) {
+      case 2: hipLaunchKernelGGL(k_ifft_pass<2>, dim3(grid_for(nthreads)), dim3(256), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
+      case 4: hipLaunchKernelGGL(k_ifft_pass<4>, dim3(grid_for(nthreads)), dim3(256), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
+      case 8: hipLaunchKernelGGL(k_ifft_pass<8>, dim3(grid_for(nthreads)), dim3(256), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
+      default: hipLaunchKernelGGL(k_ifft_pass<16>, dim3(grid_for(nthreads)), dim3(256), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    Ns *= rs;
+    double2* tmpb = src; src = dst; dst = tmpb;
+  }
+  hipLaunchKernelGGL(k_real_part, dim3(grid_for((int64_t)g.d * g.b)), dim3(256), 0, s, src,
+                     1.0 / (double)g.b, (int64_t)g.d * g.b, c64);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- diagonal
+
+template <int DT> __device__ __forceinline__ float load_deq(const void* X, int64_t off);
+template <> __device__ __forceinline__ float load_deq<0>(const void* X, int64_t off) {
+  return ((const float*)X)[off];
+}
+template <> __device__ __forceinline__ float load_deq<1>(const void* X, int64_t off) {
+  return __uint_as_float((uint32_t)((const uint16_t*)X)[off] << 16);
+}
+template <> __device__ __forceinline__ float load_deq<2>(const void* X, int64_t off) {
+  uint32_t v = ((const uint8_t*)X)[off];
+  uint32_t sign = (v & 0x80u) << 24;
+  uint32_t e = (v >> 3) & 0xFu, mnt = v & 7u;
+  float mag;
+  if (e == 0) mag = (float)mnt * 0x1p-9f;
+  else if (e == 15 && mnt == 7) mag = __uint_as_float(0x7FC00000u);
+  else mag = __uint_as_float(((e + 120u) << 23) | (mnt << 20));
+  return __uint_as_float(__float_as_uint(mag) | sign);
+}
+
+// partial[kc][i] = sum over k in chunk kc of A[i,k] B[k,i] (float64)
+template <int DT>
+__global__ void k_diag_partial(const void* A, int64_t lda, const float* sA, const void* B,
+                               int64_t ldb, const float* sB, int m, int n, int kchunks,
+                               double* __restrict__ partial) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int kc = blockIdx.y;
+  if (i >= n) return;
+  const int k0 = (int)((int64_t)m * kc / kchunks), k1 = (int)((int64_t)m * (kc + 1) / kchunks);
+  // the operand values are float32(decoded element * scale), as in the sketch
+  const float fa = sA ? sA[i] : 1.0f, fb = sB ? sB[i] : 1.0f;
+  double acc = 0.0;
+  for (int k = k0; k < k1; ++k)
+    acc += (double)(load_deq<DT>(A, (int64_t)k * lda + i) * fa) *
+           (double)(load_deq<DT>(B, (int64_t)k * ldb + i) * fb);
+  partial[(int64_t)kc * n + i] = acc;
+}
+
+__global__ void k_diag_reduce(const double* __restrict__ partial, int n, int kchunks,
+                              double* __restrict__ diag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int kc = 0; kc < kchunks; ++kc) s += partial[(int64_t)kc * n + i];
+  diag[i] = s;
+}
+
+hipError_t launch_diag(int dtype, const SideDesc& a, const SideDesc& bs, int m, int n,
+                       double* partial, int kchunks, double* diag, hipStream_t s) {
+  dim3 grid((n + 255) / 256, kchunks);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_diag_partial<0>, grid, dim3(256), 0, s, a.X, a.ld, a.scale, bs.X, bs.ld, bs.scale, m, n, kchunks, partial);
+  else if (dtype == 1)
+    hipLaunchKernelGGL(k_diag_partial<1>, grid, dim3(256), 0, s, a.X, a.ld, a.scale, bs.X, bs.ld, bs.scale, m, n, kchunks, partial);
+  else
+    hipLaunchKernelGGL(k_diag_partial<2>, grid, dim3(256), 0, s, a.X, a.ld, a.scale, bs.X, bs.ld, bs.scale, m, n, kchunks, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_reduce, dim3((n + 255) / 256), dim3(256), 0, s, partial, n, kchunks, diag);
+  return hipGetLastError();
+}
+
+// c_t[(h1(i) + h2(i)) mod b] -= s1(i) s2(i) diag[i]
+__global__ void k_sub_diag(const int32_t* __restrict__ hs1, const int32_t* __restrict__ hs2,
+                           int n1, int n3, const double* __restrict__ diag, int len, int d,
+                           int64_t b, double* __restrict__ c64) {
+  const int64_t total = (int64_t)d * len;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(idx / len);
+    const int i = (int)(idx - (int64_t)t * len);
+    const int32_t a = hs1[(int64_t)t * n1 + i], c = hs2[(int64_t)t * n3 + i];
+    const int64_t u = (int64_t)((a >> 1) + (c >> 1)) & (b - 1);
+    const double v = ((a ^ c) & 1) ? diag[i] : -diag[i];
+    atomicAdd(&c64[(int64_t)t * b + u], v);
+  }
+}
+
+hipError_t launch_sub_diag(const Geometry& g, const int32_t* hs1, const int32_t* hs2, int n1,
+                           int n3, const double* diag, int len, double* c64, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_diag, dim3(grid_for((int64_t)g.d * len)), dim3(256), 0, s, hs1, hs2,
+                     n1, n3, diag, len, g.d, g.b, c64);
+  return hipGetLastError();
+}
+
+__global__ void k_to_f32(const double* __restrict__ c64, float* __restrict__ c32, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    c32[i] = (float)c64[i];
+}
+
+hipError_t launch_to_f32(const double* c64, float* c32, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(count)), dim3(256), 0, s, c64, c32, count);
+  return hipGetLastError();
+}
+
+__global__ void k_add_f64(double* __restrict__ dst, const double* __restrict__ src, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] += src[i];
+}
+
+hipError_t launch_add_f64(double* dst, const double* src, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_f64, dim3(grid_for(count)), dim3(256), 0, s, dst, src, count);
+  return hipGetLastError();
+}
+
+}  // namespace cmm

@@ -195,9 +195,7 @@ def _encode(mat_kmajor: np.ndarray, dtype: str):
         amax = np.abs(mat_kmajor).max(axis=0)
         scale = np.where(amax > 0, amax / 448.0, 1.0).astype(np.float32)
         s = e4m3fn_encode(mat_kmajor / scale.astype(np.float64)[None, :])
-        mag = _E4M3[(s & 0x7F).astype(np.int64)]
-        deq = np.where((s & 0x80) != 0, -mag, mag) * scale.astype(np.float64)[None, :]
-        return s, scale, deq
+        return s, scale, _decode_store(s, "fp8", scale)[2]
     raise ValueError(dtype)
 
 
@@ -235,7 +233,8 @@ def _decode_store(store, dtype, scale):
     if dtype == "bf16":
         return store, None, (store.astype(np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
     mag = _E4M3[(store & 0x7F).astype(np.int64)]
-    return store, scale, np.where((store & 0x80) != 0, -mag, mag) * scale.astype(np.float64)[None, :]
+    val = np.where((store & 0x80) != 0, -mag, mag).astype(np.float32) * scale.astype(np.float32)[None, :]
+    return store, scale, val.astype(np.float64)
 
 
 # The five workloads of the benchmark plan.  Data seed 1000+cfg, hash seed
