@@ -34,7 +34,7 @@
  *   per repetition and per function h1, s1, h2, s2 (in that order).  With a
  *   seed the pairs come from the SplitMix64 stream of the seed: outputs
  *   z_{8t+2f+1}, z_{8t+2f+2} give a = 1 + z mod (2^61-2), c = z' mod (2^61-1).
- * - b must be a power of two in [16, 2^22]; 1 <= d <= 63.
+ * - b must be a power of two in [16, 2^20]; 1 <= d <= 63.
  * - Objects are library-owned: free sketches with cmm_sketch_free() before
  *   destroying their context with cmm_ctx_destroy().
  */

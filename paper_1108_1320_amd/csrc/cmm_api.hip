@@ -177,6 +177,7 @@ cmm::Geometry make_geometry(int64_t b, int d, int64_t m) {
   g.rows = g.R > 1 ? g.R / 2 + 1 : 1;
   const int64_t base = (int64_t)d * g.rows;
   int64_t ks = std::max<int64_t>(1, (2048 + base - 1) / base);
+  ks = std::max<int64_t>(ks, (m + cmm::kMaxKPerBlock - 1) / cmm::kMaxKPerBlock);
   ks = std::min<int64_t>(ks, m);
   while (ks < m && (base * ks) % 8 != 0) ++ks;
   g.KS = (int)std::max<int64_t>(1, ks);
@@ -214,7 +215,7 @@ int check_operands(cmm_ctx* c, const void* A, int64_t lda, const void* B, int64_
     return fail(c, CMM_EUNSUPPORTED, "dimensions too large");
   if (lda < n1 || ldb < n3) return fail(c, CMM_EINVAL, "lda < n1 or ldb < n3");
   if (dtype < CMM_F32 || dtype > CMM_FP8_E4M3) return fail(c, CMM_EINVAL, "unknown dtype");
-  if (!is_pow2(b) || b < 16 || b > (1 << 22)) return fail(c, CMM_EINVAL, "b must be a power of two in [16, 2^22]");
+  if (!is_pow2(b) || b < 16 || b > (1 << 20)) return fail(c, CMM_EINVAL, "b must be a power of two in [16, 2^20]");
   if (d < 1 || d > 63) return fail(c, CMM_EINVAL, "d must be in [1, 63]");
   if (std::max(n1, n3) * (int64_t)sizeof(float) > 96 * 1024)
     return fail(c, CMM_EUNSUPPORTED, "hashed dimension above 24576 (count-sketch row staging)");
@@ -252,11 +253,12 @@ int run_product(cmm_ctx* c, cmm_sketch* sk, const void* A, int64_t lda, const vo
     sd.segcount = w.get<int32_t>((size_t)g.d * g.W);
     sd.lseg = w.get<int32_t>((size_t)g.d);
     sd.SA = w.get<float>((size_t)g.d * g.m * sd.Lrow);
-    if (!sd.cnt || !sd.pos || !sd.ent || !sd.tab || !sd.cntp || !sd.moff || !sd.fill || !sd.perm ||
+    sd.colmax = w.get<float>((size_t)g.d * g.m);
+    if (!sd.colmax || !sd.cnt || !sd.pos || !sd.ent || !sd.tab || !sd.cntp || !sd.moff || !sd.fill || !sd.perm ||
         !sd.segcount || !sd.lseg || !sd.SA)
       return fail(c, CMM_ENOMEM, "workspace allocation failed");
   }
-  double2* Ppart = w.get<double2>((size_t)g.d * g.KS * g.rows * C);
+  float2* Ppart = w.get<float2>((size_t)g.d * g.KS * g.rows * C);
   double2* work0 = w.get<double2>((size_t)g.d * g.b);
   double2* work1 = w.get<double2>((size_t)g.d * g.b);
   int32_t* oflow = w.get<int32_t>(1);

@@ -10,7 +10,8 @@
 //   ent[side][t][p]       uint32 bucket id at layout position p (bit 31 = padding)
 //   tab[side][t][p]       uint32 first member | sign << 31 | more-members << 30
 //   SA[side][t][k][p]     float  count sketch of column k (side 0) / row k (side 1)
-//   Ppart[t][ks][f1][f2]  double2 partial spectral sums of one k-split
+//   colmax[side][t][k]    float  max |SA[side][t][k][.]| (fixed-point scale of the fold)
+//   Ppart[t][ks][f1][f2]  float2 partial spectral sums of one k-split (<= 128 k)
 //   c64[t][u], c32[t][u]  the sketch
 //
 // Layout positions: the fused FFT kernel works on C-point rows with T = C/16
@@ -34,6 +35,7 @@ namespace cmm {
 
 constexpr int kMaxLog2C = 12;          // FFT row length C <= 4096
 constexpr int kTopkCap = 4096;         // candidates sorted by the final top-K pass
+constexpr int kMaxKPerBlock = 128;     // k per FFT block (float32 partial sums)
 
 struct SideDesc {
   const void* X;        // stored operand (k-major rows of length n)
@@ -52,6 +54,7 @@ struct SideDesc {
   int32_t* segcount;    // [d][W]
   int32_t* lseg;        // [d]
   float* SA;            // [d][m][Lrow]
+  float* colmax;        // [d][m] max |SA| of each sketched column / row
   int Lcap;             // positions per segment
   int Lrow;             // W * Lcap
 };
@@ -79,8 +82,8 @@ hipError_t launch_count(const Geometry& g, SideDesc& sd, hipStream_t s);
 hipError_t launch_layout(const Geometry& g, SideDesc& sd, int32_t* overflow, hipStream_t s);
 hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStream_t s);
 hipError_t launch_fft_mac(const Geometry& g, const SideDesc& a, const SideDesc& bside,
-                          const float2* tw32, double2* Ppart, hipStream_t s);
-hipError_t launch_ifft(const Geometry& g, const double2* Ppart, double2* work0, double2* work1,
+                          const float2* tw32, float2* Ppart, hipStream_t s);
+hipError_t launch_ifft(const Geometry& g, const float2* Ppart, double2* work0, double2* work1,
                        const double2* tw64, double* c64, hipStream_t s);
 hipError_t launch_diag(int dtype, const SideDesc& a, const SideDesc& bside, int m, int n,
                        double* partial, int kchunks, double* diag, hipStream_t s);

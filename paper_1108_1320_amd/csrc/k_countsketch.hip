@@ -52,6 +52,7 @@ template <> struct Elem<2> {      // fp8 e4m3fn bits
 template <int DT, bool VEC>
 __global__ __launch_bounds__(256) void k_countsketch(SideDesc sd, int d, int m, int W, int kblock) {
   extern __shared__ float row[];
+  __shared__ float red[4];
   typedef Elem<DT> E;
   const int tid = threadIdx.x;
   const int n = sd.n;
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(256) void k_countsketch(SideDesc sd, int d, int m, 
       const int total = W * L;
       const uint32_t* tab = sd.tab + (int64_t)t * sd.Lrow;
       float* out = sd.SA + ((int64_t)t * m + k) * sd.Lrow;
+      float amax = 0.0f;
       for (int idx = tid; idx < total; idx += 256) {
         const int w = idx / L;
         const int p = w * sd.Lcap + (idx - w * L);
@@ -105,7 +107,14 @@ __global__ __launch_bounds__(256) void k_countsketch(SideDesc sd, int d, int m, 
           }
         }
         out[p] = v;
+        amax = fmaxf(amax, fabsf(v));
       }
+      // block max of |v| -> colmax[t][k]
+      for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
+      if ((tid & 63) == 0) red[tid >> 6] = amax;
+      __syncthreads();
+      if (tid == 0) sd.colmax[(int64_t)t * m + k] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+      __syncthreads();
     }
     __syncthreads();
   }

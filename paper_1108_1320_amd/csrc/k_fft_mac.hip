@@ -12,34 +12,48 @@
 // so every "row" f1 is a weighted fold of the sketch's non-zero entries into
 // C slots followed by one C-point FFT in LDS.  x is real, so rows
 // f1 in [0, R/2] carry the whole spectrum (X[b - f] = conj X[f]).  One
-// block owns one (repetition t, row f1, range of k): for each k it folds the
-// column sketch of A and the row sketch of B, transforms both, multiplies
-// them bin by bin and adds the products into float64 accumulators held in
-// registers.  The n-by-b spectra are never stored.
+// block owns one (repetition t, row f1, range of at most 128 k): for each k
+// it folds the column sketch of A and the row sketch of B, transforms both,
+// multiplies them bin by bin and adds the products into float32
+// accumulators held in registers; the per-block partial sums are added in
+// float64 afterwards.  The n-by-b spectra are never stored.
 //
 // FFT: Stockham autosort, T = C/16 threads with 16 complex values each; the
 // first stage has radix 2^(log2 C mod 4) (if not zero) and the rest radix
-// 16, with LDS exchanges (padded by one element per 16) between stages.
-// Thread j starts with slots j + T v and ends with frequencies j + T v.
+// 16, with LDS exchanges (xor-swizzled) between stages.  Thread j starts
+// with slots j + T v and ends with frequencies j + T v.
 //
 // Fold: the slots of thread j are exactly the buckets u with u mod T = j.
 // The bucket layout hands every wave only buckets whose slots belong to its
-// own lanes, so a wave's LDS float atomics never race with another wave's
-// and the wave's in-order LDS queue makes the fold's summation order fixed.
+// own lanes, so a wave's LDS atomics never touch another wave's slots; the
+// sums are exact integer (fixed-point) sums, independent of their order.
 #include "cmm_internal.h"
 #include "cmm_dft.h"
 
 namespace cmm {
 
-__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+// LDS index swizzle: xor the low 4 bits with bits 4..7.  Rows of 16
+// consecutive complex values stay rows (stage reads at j + T v are
+// conflict-free) and the stride-16 writes of the first radix-16 stage spread
+// over all banks.
+__device__ __forceinline__ int sw(int i) { return i ^ ((i >> 4) & 15); }
+
+// LDS address of slot j + T q (the own positions of thread j).  For T a
+// multiple of 256 the swizzle leaves the T q part alone, so the address is
+// one base plus an immediate offset.
+template <int T> __device__ __forceinline__ int own(int jbase, int j, int q) {
+  if constexpr (T % 256 == 0) return jbase + T * q;
+  else return sw(j + T * q);
+}
 
 struct FftArgs {
   const float* SA0; const float* SA1;
   const uint32_t* ent0; const uint32_t* ent1;
   const int32_t* lseg0; const int32_t* lseg1;
+  const float* cmax0; const float* cmax1;
   int Lcap0, Lcap1, Lrow0, Lrow1;
   const float2* tw;        // omega_b^x for x < b
-  double2* Ppart;
+  float2* Ppart;
   int64_t b;
   int R, rows, d, m, KS, nwg, remap;
 };
@@ -52,16 +66,17 @@ template <int L> struct FftShape {
   static constexpr int E = L % 4;
   static constexpr int S = L / 4 + (E ? 1 : 0);
   static constexpr int G = T < 64 ? T : 64;
-  static constexpr int BUF = C + C / 16;
-  static constexpr int NTW = S > 1 ? S - 1 : 1;
-  // span of stage s (product of the earlier radices)
   static constexpr int span(int s) { return s == 0 ? 1 : (E ? (1 << E) : 16) * ipow16(s - 1); }
   static constexpr int radix(int s) { return (s == 0 && E) ? (1 << E) : 16; }
+  // twiddle table of the middle stage 1 (present when S == 3)
+  static constexpr int NMID = S >= 3 ? 15 * ((E ? (1 << E) : 16)) : 0;
 };
 
 template <int L, int s> struct Stage {
+  // tl: last-stage twiddles (registers); tm: middle-stage table in LDS,
+  // tm[(r - 1) * Ns + (j mod Ns)] = omega_{16 Ns}^((j mod Ns) r)
   static __device__ __forceinline__ void run(float2* v, float2* P0, float2* P1,
-                                             const float2 (&tw)[FftShape<L>::NTW][15], int j) {
+                                             const float2 (&tl)[15], const float2* tm, int j) {
     typedef FftShape<L> F;
     constexpr int Rs = F::radix(s);
     constexpr int BPT = 16 / Rs;
@@ -70,9 +85,15 @@ template <int L, int s> struct Stage {
     float2* bout = (s % 2 == 0) ? P1 : P0;
     if constexpr (s > 0) {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] = bin[pidx(j + F::T * q)];
+      for (int q = 0; q < 16; ++q) v[q] = bin[own<F::T>(sw(j), j, q)];
+      if constexpr (s == F::S - 1) {
 #pragma unroll
-      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw[s - 1][r - 1]);
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tl[r - 1]);
+      } else {
+        const int jm = j % Ns;
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tm[(r - 1) * Ns + jm]);
+      }
     }
 #pragma unroll
     for (int mi = 0; mi < BPT; ++mi) {
@@ -90,22 +111,78 @@ template <int L, int s> struct Stage {
         const int jb = j + F::T * mi;
         const int base = (jb / Ns) * Ns * Rs + (jb % Ns);
 #pragma unroll
-        for (int r = 0; r < Rs; ++r) bout[pidx(base + r * Ns)] = v[mi + r * BPT];
+        for (int r = 0; r < Rs; ++r) bout[sw(base + r * Ns)] = v[mi + r * BPT];
       }
       __syncthreads();
-      Stage<L, s + 1>::run(v, P0, P1, tw, j);
+      Stage<L, s + 1>::run(v, P0, P1, tl, tm, j);
     }
   }
 };
 
+// Entries of the fold are fetched U per lane at a time; the first batch of
+// the next (side, k) is issued before the current transform so its latency
+// hides behind the FFT.
+constexpr int kU = 8;
+
+struct Batch {
+  float v[kU];
+  uint32_t u[kU];
+};
+
+template <int G>
+__device__ __forceinline__ void fetch(Batch& bt, const float* sa, const uint32_t* en, int ls,
+                                      int lane, int first) {
+#pragma unroll
+  for (int i = 0; i < kU; ++i) {
+    const int it = lane + G * (first + i);
+    if (it < ls) { bt.v[i] = sa[it]; bt.u[i] = en[it]; }
+    else { bt.v[i] = 0.0f; bt.u[i] = 0xFFFFFFFFu; }
+  }
+}
+
+// Fold weight of entry u in row f1: omega_b^(f1 r) omega_R^(f1 q) with
+// r = u mod C, q = u div C equals omega_b^(f1 j) * omega_16R^(f1 v) with
+// j = u mod T (the owning thread) and v = u div T; the first factor is
+// common to all slots of thread j and applied once per slot after the fold,
+// the second comes from the 16R-entry table w16.
+//
+// The fold adds in fixed point with LDS integer atomics (float LDS atomics
+// are an order of magnitude slower, and integer sums do not depend on the
+// order of the adds).  A slot gathers at most R buckets and |w| = 1, so with
+// the column's max |value| cmax the slot sums stay below R cmax; values are
+// scaled by 2^(30 - e) with R cmax < 2^e and rounded to int32.
+template <int L, int G>
+__device__ __forceinline__ void fold(const Batch& bt, int2* Z, int f1, int m16,
+                                     const float2* w16, float scale) {
+  constexpr int C = 1 << L;
+  constexpr int LT = L - 4;          // log2 T
+#pragma unroll
+  for (int i = 0; i < kU; ++i) {
+    const uint32_t u = bt.u[i];
+    if (u == 0xFFFFFFFFu) continue;
+    const uint32_t uu = u & 0x7FFFFFFFu;
+    int2* dst = &Z[sw((int)(uu & (C - 1)))];
+    const float sv = bt.v[i] * scale;
+    if (f1 == 0) {
+      atomicAdd(&dst->x, __float2int_rn(sv));
+    } else {
+      const float2 w = w16[(f1 * (int)(uu >> LT)) & m16];
+      atomicAdd(&dst->x, __float2int_rn(sv * w.x));
+      atomicAdd(&dst->y, __float2int_rn(sv * w.y));
+    }
+  }
+}
+
 template <int L>
-__global__ __launch_bounds__(FftShape<L>::T) void k_fft_mac(FftArgs a) {
+__global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   typedef FftShape<L> F;
   constexpr int C = F::C, T = F::T, G = F::G;
   extern __shared__ float2 lds[];
   float2* P0 = lds;
-  float2* P1 = lds + F::BUF;
-  float2* wr = lds + 2 * F::BUF;
+  float2* P1 = lds + C;
+  float2* tm = lds + 2 * C;
+  float2* w16 = tm + F::NMID;        // omega_16R^x, x < 16 R
+  static_assert(F::S <= 3, "one middle stage at most");
 
   const int bid = blockIdx.x;
   const int logical = a.remap ? (bid & 7) * (a.nwg >> 3) + (bid >> 3) : bid;
@@ -120,78 +197,92 @@ __global__ __launch_bounds__(FftShape<L>::T) void k_fft_mac(FftArgs a) {
   const int kb = (int)((int64_t)a.m * ks / a.KS);
   const int ke = (int)((int64_t)a.m * (ks + 1) / a.KS);
 
-  for (int q = j; q < R; q += T) wr[q] = a.tw[(int64_t)q * C];
-  float2 st[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) st[q] = a.tw[((uint64_t)f1 * (uint64_t)(j + T * q)) & bm];
-  float2 tw[F::NTW][15];
-#pragma unroll
-  for (int s = 1; s < F::S; ++s) {
-    const int Ns = F::span(s);
+  const int m16 = 16 * R - 1;
+  for (int q = j; q < 16 * R; q += T) w16[q] = a.tw[(int64_t)q * T];
+  const float2 sj = a.tw[((uint64_t)f1 * (uint64_t)j) & bm];   // omega_b^(f1 j)
+  const int jbase = sw(j);
+  // last-stage twiddles omega_C^((j mod Ns) r), Ns = span(S-1)
+  float2 tl[15];
+  if constexpr (F::S >= 2) {
+    constexpr int Ns = F::span(F::S - 1);
 #pragma unroll
     for (int r = 1; r < 16; ++r)
-      tw[s - 1][r - 1] = a.tw[(int64_t)((j % Ns) * r) * (C / (16 * Ns)) * R];
+      tl[r - 1] = a.tw[(int64_t)((j % Ns) * r) * (C / (16 * Ns)) * R];
+  }
+  if constexpr (F::NMID > 0) {
+    constexpr int Ns = F::span(1);
+    for (int e = j; e < F::NMID; e += T) {
+      const int r = e / Ns + 1, jm = e % Ns;
+      tm[e] = a.tw[(int64_t)(jm * r) * (C / (16 * Ns)) * R];
+    }
   }
   __syncthreads();
 
-  double2 acc[16];
+  float2 acc[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = make_double2(0.0, 0.0);
-  const bool realw = (f1 == 0) || (2 * f1 == R);
+  for (int q = 0; q < 16; ++q) acc[q] = make_float2(0.f, 0.f);
+
+  const float* sa0 = a.SA0 + (int64_t)t * a.m * a.Lrow0 + wv * a.Lcap0;
+  const float* sa1 = a.SA1 + (int64_t)t * a.m * a.Lrow1 + wv * a.Lcap1;
+  const uint32_t* en0 = a.ent0 + (int64_t)t * a.Lrow0 + wv * a.Lcap0;
+  const uint32_t* en1 = a.ent1 + (int64_t)t * a.Lrow1 + wv * a.Lcap1;
+  const int ls0 = a.lseg0[t], ls1 = a.lseg1[t];
+  const float* cm0 = a.cmax0 + (int64_t)t * a.m;
+  const float* cm1 = a.cmax1 + (int64_t)t * a.m;
+  int2* Z = reinterpret_cast<int2*>(P0);
+
+  Batch bt;
+  if (kb < ke) fetch<G>(bt, sa0 + (int64_t)kb * a.Lrow0, en0, ls0, lane, 0);
 
   for (int k = kb; k < ke; ++k) {
     float2 X[16];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
-      const float* sa = (side == 0 ? a.SA0 : a.SA1) +
-                        ((int64_t)t * a.m + k) * (side == 0 ? a.Lrow0 : a.Lrow1) +
-                        wv * (side == 0 ? a.Lcap0 : a.Lcap1);
-      const uint32_t* en = (side == 0 ? a.ent0 : a.ent1) +
-                           (int64_t)t * (side == 0 ? a.Lrow0 : a.Lrow1) +
-                           wv * (side == 0 ? a.Lcap0 : a.Lcap1);
-      const int ls = (side == 0 ? a.lseg0 : a.lseg1)[t];
+      const float* sa = side == 0 ? sa0 + (int64_t)k * a.Lrow0 : sa1 + (int64_t)k * a.Lrow1;
+      const uint32_t* en = side == 0 ? en0 : en1;
+      const int ls = side == 0 ? ls0 : ls1;
+      // fixed-point scale 2^(30 - e) with R * cmax < 2^e
+      int ex;
+      const float bound = (float)R * (side == 0 ? cm0[k] : cm1[k]);
+      (void)frexpf(bound, &ex);
+      const float scale = bound > 0.0f ? ldexpf(1.0f, 30 - ex) : 0.0f;
+      const float inv = bound > 0.0f ? ldexpf(1.0f, ex - 30) : 0.0f;
       float2 v[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) P0[pidx(j + T * q)] = make_float2(0.f, 0.f);
+      for (int q = 0; q < 16; ++q) Z[own<T>(jbase, j, q)] = make_int2(0, 0);
       __builtin_amdgcn_wave_barrier();
-      if (realw) {
-        for (int it = lane; it < ls; it += G) {
-          float val = sa[it];
-          const uint32_t u = en[it] & 0x7FFFFFFFu;
-          if (f1 != 0 && ((u >> L) & 1u)) val = -val;
-          atomicAdd(&P0[pidx((int)(u & (C - 1)))].x, val);
-        }
-      } else {
-        for (int it = lane; it < ls; it += G) {
-          const float val = sa[it];
-          const uint32_t u = en[it] & 0x7FFFFFFFu;
-          const float2 w = wr[(f1 * (int)(u >> L)) & (R - 1)];
-          float2* dst = &P0[pidx((int)(u & (C - 1)))];
-          atomicAdd(&dst->x, val * w.x);
-          atomicAdd(&dst->y, val * w.y);
-        }
+      fold<L, G>(bt, Z, f1, m16, w16, scale);
+      for (int first = kU; first * G < ls; first += kU) {
+        fetch<G>(bt, sa, en, ls, lane, first);
+        fold<L, G>(bt, Z, f1, m16, w16, scale);
       }
+      // first batch of the next (side, k), in flight during the transform
+      if (side == 0) fetch<G>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0);
+      else if (k + 1 < ke) fetch<G>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0);
       __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int q = 0; q < 16; ++q) v[q] = P0[pidx(j + T * q)];
+      for (int q = 0; q < 16; ++q) {
+        const int2 zi = Z[own<T>(jbase, j, q)];
+        v[q] = make_float2((float)zi.x * inv, (float)zi.y * inv);
+      }
       if (f1 != 0) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = cmul(v[q], st[q]);
+        for (int q = 0; q < 16; ++q) v[q] = cmul(v[q], sj);
       }
-      Stage<L, 0>::run(v, P0, P1, tw, j);
+      Stage<L, 0>::run(v, P0, P1, tl, tm, j);
       if (side == 0) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) X[q] = v[q];
       } else {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-          acc[q].x += (double)(X[q].x * v[q].x - X[q].y * v[q].y);
-          acc[q].y += (double)(X[q].x * v[q].y + X[q].y * v[q].x);
+          acc[q].x = fmaf(X[q].x, v[q].x, fmaf(-X[q].y, v[q].y, acc[q].x));
+          acc[q].y = fmaf(X[q].x, v[q].y, fmaf(X[q].y, v[q].x, acc[q].y));
         }
       }
     }
   }
-  double2* out = a.Ppart + (((int64_t)t * a.KS + ks) * a.rows + f1) * C;
+  float2* out = a.Ppart + (((int64_t)t * a.KS + ks) * a.rows + f1) * C;
 #pragma unroll
   for (int q = 0; q < 16; ++q) out[j + T * q] = acc[q];
 }
@@ -199,7 +290,7 @@ __global__ __launch_bounds__(FftShape<L>::T) void k_fft_mac(FftArgs a) {
 template <int L>
 static hipError_t launch_L(const FftArgs& a, hipStream_t s) {
   typedef FftShape<L> F;
-  const size_t lds = (size_t)(2 * F::BUF + a.R) * sizeof(float2);
+  const size_t lds = (size_t)(2 * F::C + F::NMID + 16 * a.R) * sizeof(float2);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_mac<L>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -210,11 +301,12 @@ static hipError_t launch_L(const FftArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc& sb,
-                          const float2* tw32, double2* Ppart, hipStream_t s) {
+                          const float2* tw32, float2* Ppart, hipStream_t s) {
   FftArgs a;
   a.SA0 = sa.SA; a.SA1 = sb.SA;
   a.ent0 = sa.ent; a.ent1 = sb.ent;
   a.lseg0 = sa.lseg; a.lseg1 = sb.lseg;
+  a.cmax0 = sa.colmax; a.cmax1 = sb.colmax;
   a.Lcap0 = sa.Lcap; a.Lcap1 = sb.Lcap; a.Lrow0 = sa.Lrow; a.Lrow1 = sb.Lrow;
   a.tw = tw32; a.Ppart = Ppart; a.b = g.b;
   a.R = g.R; a.rows = g.rows; a.d = g.d; a.m = g.m; a.KS = g.KS;

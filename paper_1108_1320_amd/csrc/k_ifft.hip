@@ -14,7 +14,7 @@
 namespace cmm {
 
 // Psum[t][f1][f2] = sum over ks of Ppart[t][ks][f1][f2]
-__global__ void k_reduce_splits(const double2* __restrict__ Ppart, int KS, int rows, int C,
+__global__ void k_reduce_splits(const float2* __restrict__ Ppart, int KS, int rows, int C,
                                 int d, double2* __restrict__ Psum) {
   const int64_t per_t = (int64_t)rows * C;
   const int64_t total = (int64_t)d * per_t;
@@ -22,11 +22,11 @@ __global__ void k_reduce_splits(const double2* __restrict__ Ppart, int KS, int r
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int t = (int)(idx / per_t);
     const int64_t rest = idx - (int64_t)t * per_t;
-    const double2* src = Ppart + (int64_t)t * KS * per_t + rest;
+    const float2* src = Ppart + (int64_t)t * KS * per_t + rest;
     double sx = 0.0, sy = 0.0;
     for (int ks = 0; ks < KS; ++ks) {
-      const double2 v = src[(int64_t)ks * per_t];
-      sx += v.x; sy += v.y;
+      const float2 v = src[(int64_t)ks * per_t];
+      sx += (double)v.x; sy += (double)v.y;
     }
     Psum[idx] = make_double2(sx, sy);
   }
@@ -93,7 +93,7 @@ static inline unsigned grid_for(int64_t n, int64_t cap = 16384) {
   return (unsigned)g;
 }
 
-hipError_t launch_ifft(const Geometry& g, const double2* Ppart, double2* work0, double2* work1,
+hipError_t launch_ifft(const Geometry& g, const float2* Ppart, double2* work0, double2* work1,
                        const double2* tw64, double* c64, hipStream_t s) {
   const int C = 1 << g.log2c;
   const int64_t nsum = (int64_t)g.d * g.rows * C;
