@@ -11,8 +11,10 @@ samples with 64 planted correlated pairs, float32, b = 2^16, d = 5, top-64
 over i < j with the diagonal subtracted.  A and B are two distinct device
 buffers holding the observation matrix.
 
-Prints one JSON line (see the keys below).  ``value`` is the input GB/s of the
-whole step: bytes(A) + bytes(B) as stored, divided by the step time.
+Prints one JSON line.  ``value`` is the input GB/s of the whole step:
+bytes(A) + bytes(B) as stored, divided by the step time.  The same workload
+is also run with bf16 operands (``bf16_same_workload``) and both are checked
+against the float64 oracle.
 """
 from __future__ import annotations
 
@@ -29,6 +31,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 METRIC = "sketch-product input GB/s (% HBM peak), BF16 vs FP32 at equal error"
+KERNELS = ("hash", "layout", "countsketch", "fft_mac", "ifft", "decode")
 
 
 def nominal_fft_mac_flop(m: int, b: int, d: int) -> float:
@@ -50,17 +53,99 @@ def parse():
     p.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4])
     p.add_argument("--dtype", default=None, help="override the workload's dtype (f32/bf16/fp8)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-compare", action="store_true", help="skip the bf16 run of the same workload")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return p.parse_args()
+
+
+def copy_calibration():
+    """A plain copy kernel of known size: 2^28 float32 values (1 GiB read,
+    1 GiB written), launched 3 times.  Its FETCH_SIZE / WRITE_SIZE counters
+    convert the counters of the measured kernels to bytes."""
+    import torch
+    x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
+                      "launches": 3}), flush=True)
+
+
+def run_timed(ctx, w, steps, warmup):
+    """Time ``steps`` whole steps (after ``warmup``) of workload ``w`` with the
+    library's kernel timing events on; returns the last product for checks."""
+    import numpy as np
+    import torch
+    import paper_1108_1320_amd as cmm
+    esz = {"f32": 4, "bf16": 2, "fp8": 1}[w.dtype]
+    At = torch.from_numpy(np.ascontiguousarray(w.At_store)).cuda()
+    Bd = torch.from_numpy(np.ascontiguousarray(w.B_store)).cuda()
+    if w.same_operand:
+        Bd = At.clone()   # a second buffer: B is read from its own memory
+    sA = torch.from_numpy(w.scaleA).cuda() if w.scaleA is not None else None
+    sB = torch.from_numpy(w.scaleB).cuda() if w.scaleB is not None else None
+
+    def step():
+        sk = cmm.sketch_product(ctx, At, Bd, w.b, w.d, seed=w.seed, dtype=w.dtype, scaleA=sA,
+                                scaleB=sB, subtract_diag=w.subtract_diag, n1=w.n1, n3=w.n3, m=w.m)
+        return sk, sk.topk(w.K, w.mode)
+
+    for _ in range(warmup):
+        sk, _ = step()
+        sk.free()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sk, res = step()
+        sk.free()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {k: ctx.profile_read(k) for k in KERNELS}
+    ctx.profile(False)
+    sk, res = step()     # one more product, kept for the checks
+    return {"ms": (t1 - t0) * 1e3 / steps, "kern": kern, "sketch": sk, "topk": res,
+            "input_bytes": (w.n1 * w.m + w.m * w.n3) * esz}
+
+
+def traffic_record(w):
+    """HBM bytes per fft_mac launch from the committed rocprofv3 counter
+    summary, if it was taken on this workload and the kernel source has not
+    changed since (else None)."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "fft_mac_cov4096_f32_traffic.json")
+    src = os.path.join(ROOT, "paper_1108_1320_amd", "csrc", "k_fft_mac.hip")
+    if not (w.name == "cfg2" and w.dtype == "f32" and os.path.exists(rec_path)):
+        return None
+    rec = json.load(open(rec_path))
+    if rec.get("source_sha256_16") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
+        return None
+    return rec["read_bytes"] + rec["write_bytes"]
+
+
+def planted_recall(w, oi, oj):
+    """Fraction of planted correlated pairs found in the top-K (covariance)."""
+    if w.planted is None or w.mode != "upper":
+        return None
+    got = {(int(min(a, c)), int(max(a, c))) for a, c in zip(oi, oj)}
+    want = {(int(min(p, q)), int(max(p, q))) for p, q in w.planted}
+    return round(len(got & want) / max(len(want), 1), 4)
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sketch would shard over k with one all-reduce of c; not built).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import paper_1108_1320_amd as cmm
     import workloads as W
@@ -68,40 +153,11 @@ def main():
     cmm.load()
     torch.cuda.init()
     w = W.make_workload(args.workload, dtype=args.dtype)
-    esz = {"f32": 4, "bf16": 2, "fp8": 1}[w.dtype]
     n1, m, n3, b, d, K = w.n1, w.m, w.n3, w.b, w.d, w.K
-    At = torch.from_numpy(np.ascontiguousarray(w.At_store)).cuda()
-    Bd = torch.from_numpy(np.ascontiguousarray(w.B_store)).cuda()
-    if w.same_operand:
-        Bd = At.clone()   # a second buffer: B is read from its own memory
-    sA = torch.from_numpy(w.scaleA).cuda() if w.scaleA is not None else None
-    sB = torch.from_numpy(w.scaleB).cuda() if w.scaleB is not None else None
-    input_bytes = (n1 * m + m * n3) * esz
     ctx = cmm.Context(0)
-
-    def step():
-        sk = cmm.sketch_product(ctx, At, Bd, b, d, seed=w.seed, dtype=w.dtype, scaleA=sA,
-                                scaleB=sB, subtract_diag=w.subtract_diag, n1=n1, n3=n3, m=m)
-        res = sk.topk(K, w.mode)
-        return sk, res
-
-    for _ in range(args.warmup):
-        sk, _ = step()
-        sk.free()
-    torch.cuda.synchronize()
-
-    ctx.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sk, res = step()
-        sk.free()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern = {k: ctx.profile_read(k) for k in ("hash", "layout", "countsketch", "fft_mac", "ifft", "decode")}
-    ctx.profile(False)
-
-    ms = (t1 - t0) * 1e3 / args.steps
+    r = run_timed(ctx, w, args.steps, args.warmup)
+    ms, kern, input_bytes = r["ms"], r["kern"], r["input_bytes"]
+    sk, (oi, oj, ov) = r["sketch"], r["topk"]
     value = input_bytes / (ms * 1e-3) / 1e9
     fft_ms, fft_n = kern["fft_mac"]
     fft_avg_ms = fft_ms / max(fft_n, 1)
@@ -112,9 +168,6 @@ def main():
     nb = expected_nonempty(n1, b) + expected_nonempty(n3, b)
     cs_bytes = input_bytes + d * m * nb * 4
     cs_gbps = cs_bytes / (cs_avg_ms * 1e-3) / 1e9
-
-    # one more product kept for the parity check against the oracle
-    sk, (oi, oj, ov) = step()
     c_gpu = sk.c()
 
     out = {
@@ -148,7 +201,8 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": None,
+            "traffic": traffic_record(w),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flop_per_launch": flop,
             "avg_launch_ms": round(fft_avg_ms, 4),
         },
@@ -158,12 +212,43 @@ def main():
             "avg_ms": round(cs_avg_ms, 4),
         },
     }
-
+    c_ref = None
     if not args.no_cpu:
-        out["cpu_baseline"], out["parity"] = cpu_baseline(w, c_gpu, oi, oj, ov, input_bytes)
+        out["cpu_baseline"], out["parity"], c_ref = cpu_baseline(w, c_gpu, oi, oj, ov, input_bytes)
+        out["parity"]["planted_recall"] = planted_recall(w, oi, oj)
+    if not args.no_compare and w.dtype == "f32" and w.mode != "column":
+        out["bf16_same_workload"] = compare_bf16(ctx, args, w, c_ref, oi, oj, value)
     sk.free()
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def compare_bf16(ctx, args, w32, c_ref, oi32, oj32, value32):
+    """The same product with its operands stored in bf16: throughput, error
+    against the float64 oracle of the float32 operands (quantisation plus
+    arithmetic), and agreement of its top-K with the float32 path."""
+    import numpy as np
+    import workloads as W
+    store = W.bf16_encode(w32.At_store)
+    w = W.Workload(name=w32.name, n1=w32.n1, m=w32.m, n3=w32.n3, b=w32.b, d=w32.d, K=w32.K,
+                   dtype="bf16", mode=w32.mode, seed=w32.seed, subtract_diag=w32.subtract_diag,
+                   At_store=store, B_store=store, planted=w32.planted, same_operand=True)
+    r = run_timed(ctx, w, max(5, args.steps // 2), 2)
+    v = r["input_bytes"] / (r["ms"] * 1e-3) / 1e9
+    c16 = r["sketch"].c()
+    oi, oj, _ = r["topk"]
+    both = set(zip(oi.tolist(), oj.tolist())) & set(zip(oi32.tolist(), oj32.tolist()))
+    res = {"value": round(v, 3), "unit": "GB/s", "ms_per_step": round(r["ms"], 4),
+           "input_elements_per_s": round((w.n1 * w.m + w.m * w.n3) / (r["ms"] * 1e-3), 1),
+           "element_rate_vs_f32": round((v / 2.0) / (value32 / 4.0), 4),
+           "topk_overlap_with_f32": round(len(both) / w.K, 4),
+           "planted_recall": planted_recall(w, oi, oj),
+           "kernel_ms_per_step": {k: round(x[0] / max(x[1], 1), 4) for k, x in r["kern"].items()}}
+    if c_ref is not None:
+        res["max_rel_l2_c_vs_f64_oracle_of_f32_operands"] = max(
+            float(np.linalg.norm(c16[t] - c_ref[t]) / np.linalg.norm(c_ref[t])) for t in range(w.d))
+    r["sketch"].free()
+    return res
 
 
 def cpu_baseline(w, c_gpu, oi, oj, ov, input_bytes):
@@ -193,15 +278,13 @@ def cpu_baseline(w, c_gpu, oi, oj, ov, input_bytes):
     t1 = time.perf_counter()
     secs = t1 - t0
     rel = max(float(np.linalg.norm(c_gpu[t] - c_ref[t]) / np.linalg.norm(c_ref[t])) for t in range(w.d))
+    est_err = None
     if w.mode != "column":
-        ref_at = O.decode(c_ref, tabs, oi, oj)
-        est_err = float(np.abs(ov - ref_at).max())
-    else:
-        est_err = None
+        est_err = float(np.abs(ov - O.decode(c_ref, tabs, oi, oj)).max())
     base = {"value": round(input_bytes / secs / 1e9, 4), "unit": "GB/s", "cores": cores,
             "kind": "oracle", "sample": sample, "seconds": round(secs, 2)}
     parity = {"max_rel_l2_c": rel, "max_abs_err_topk_values": est_err, "tolerance": 1e-5}
-    return base, parity
+    return base, parity, c_ref
 
 
 if __name__ == "__main__":

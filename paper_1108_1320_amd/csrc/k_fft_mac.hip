@@ -66,6 +66,7 @@ template <int L> struct FftShape {
   static constexpr int E = L % 4;
   static constexpr int S = L / 4 + (E ? 1 : 0);
   static constexpr int G = T < 64 ? T : 64;
+  static constexpr int U = L == 12 ? 16 : 8;     // fold entries fetched per lane at once
   static constexpr int span(int s) { return s == 0 ? 1 : (E ? (1 << E) : 16) * ipow16(s - 1); }
   static constexpr int radix(int s) { return (s == 0 && E) ? (1 << E) : 16; }
   // twiddle table of the middle stage 1 (present when S == 3)
@@ -122,15 +123,13 @@ template <int L, int s> struct Stage {
 // Entries of the fold are fetched U per lane at a time; the first batch of
 // the next (side, k) is issued before the current transform so its latency
 // hides behind the FFT.
-constexpr int kU = 8;
-
-struct Batch {
-  float v[kU];
-  uint32_t u[kU];
+template <int U> struct Batch {
+  float v[U];
+  uint32_t u[U];
 };
 
-template <int G>
-__device__ __forceinline__ void fetch(Batch& bt, const float* sa, const uint32_t* en, int ls,
+template <int G, int kU>
+__device__ __forceinline__ void fetch(Batch<kU>& bt, const float* sa, const uint32_t* en, int ls,
                                       int lane, int first) {
 #pragma unroll
   for (int i = 0; i < kU; ++i) {
@@ -150,25 +149,35 @@ __device__ __forceinline__ void fetch(Batch& bt, const float* sa, const uint32_t
 // are an order of magnitude slower, and integer sums do not depend on the
 // order of the adds).  A slot gathers at most R buckets and |w| = 1, so with
 // the column's max |value| cmax the slot sums stay below R cmax; values are
-// scaled by 2^(30 - e) with R cmax < 2^e and rounded to int32.
-template <int L, int G>
-__device__ __forceinline__ void fold(const Batch& bt, int2* Z, int f1, int m16,
+// scaled by 2^(30 - e) with R cmax < 2^e and rounded to int32.  The real and
+// imaginary parts travel packed in one 64-bit add, im * 2^32 + re: the sum
+// is exact modulo 2^64 and both 32-bit sums are recovered from it because
+// each stays inside int32.
+__device__ __forceinline__ unsigned long long pack2(int re, int im) {
+  return (unsigned long long)(((long long)im << 32) + (long long)re);
+}
+__device__ __forceinline__ int2 unpack2(unsigned long long p) {
+  const int re = (int)(uint32_t)(p & 0xFFFFFFFFull);
+  const int im = (int)(long long)(((long long)p - (long long)re) >> 32);
+  return make_int2(re, im);
+}
+
+template <int L, int G, int kU>
+__device__ __forceinline__ void fold(const Batch<kU>& bt, unsigned long long* Z, int f1, int m16,
                                      const float2* w16, float scale) {
   constexpr int C = 1 << L;
   constexpr int LT = L - 4;          // log2 T
 #pragma unroll
   for (int i = 0; i < kU; ++i) {
     const uint32_t u = bt.u[i];
-    if (u == 0xFFFFFFFFu) continue;
-    const uint32_t uu = u & 0x7FFFFFFFu;
-    int2* dst = &Z[sw((int)(uu & (C - 1)))];
+    if ((int)u < 0) continue;        // padding or past the segment
+    unsigned long long* dst = &Z[sw((int)(u & (C - 1)))];
     const float sv = bt.v[i] * scale;
     if (f1 == 0) {
-      atomicAdd(&dst->x, __float2int_rn(sv));
+      atomicAdd(dst, (unsigned long long)(long long)__float2int_rn(sv));
     } else {
-      const float2 w = w16[(f1 * (int)(uu >> LT)) & m16];
-      atomicAdd(&dst->x, __float2int_rn(sv * w.x));
-      atomicAdd(&dst->y, __float2int_rn(sv * w.y));
+      const float2 w = w16[(f1 * (int)(u >> LT)) & m16];
+      atomicAdd(dst, pack2(__float2int_rn(sv * w.x), __float2int_rn(sv * w.y)));
     }
   }
 }
@@ -176,7 +185,7 @@ __device__ __forceinline__ void fold(const Batch& bt, int2* Z, int f1, int m16,
 template <int L>
 __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   typedef FftShape<L> F;
-  constexpr int C = F::C, T = F::T, G = F::G;
+  constexpr int C = F::C, T = F::T, G = F::G, kU = F::U;
   extern __shared__ float2 lds[];
   float2* P0 = lds;
   float2* P1 = lds + C;
@@ -229,10 +238,10 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   const int ls0 = a.lseg0[t], ls1 = a.lseg1[t];
   const float* cm0 = a.cmax0 + (int64_t)t * a.m;
   const float* cm1 = a.cmax1 + (int64_t)t * a.m;
-  int2* Z = reinterpret_cast<int2*>(P0);
+  unsigned long long* Z = reinterpret_cast<unsigned long long*>(P0);
 
-  Batch bt;
-  if (kb < ke) fetch<G>(bt, sa0 + (int64_t)kb * a.Lrow0, en0, ls0, lane, 0);
+  Batch<kU> bt;
+  if (kb < ke) fetch<G, kU>(bt, sa0 + (int64_t)kb * a.Lrow0, en0, ls0, lane, 0);
 
   for (int k = kb; k < ke; ++k) {
     float2 X[16];
@@ -249,25 +258,30 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
       const float inv = bound > 0.0f ? ldexpf(1.0f, ex - 30) : 0.0f;
       float2 v[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) Z[own<T>(jbase, j, q)] = make_int2(0, 0);
+      for (int q = 0; q < 16; ++q) Z[own<T>(jbase, j, q)] = 0ull;
       __builtin_amdgcn_wave_barrier();
-      fold<L, G>(bt, Z, f1, m16, w16, scale);
+      fold<L, G, kU>(bt, Z, f1, m16, w16, scale);
       for (int first = kU; first * G < ls; first += kU) {
-        fetch<G>(bt, sa, en, ls, lane, first);
-        fold<L, G>(bt, Z, f1, m16, w16, scale);
+        fetch<G, kU>(bt, sa, en, ls, lane, first);
+        fold<L, G, kU>(bt, Z, f1, m16, w16, scale);
       }
       // first batch of the next (side, k), in flight during the transform
-      if (side == 0) fetch<G>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0);
-      else if (k + 1 < ke) fetch<G>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0);
+      if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0);
+      else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0);
       __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int2 zi = Z[own<T>(jbase, j, q)];
-        v[q] = make_float2((float)zi.x * inv, (float)zi.y * inv);
-      }
       if (f1 != 0) {
+        const float2 sjs = make_float2(sj.x * inv, sj.y * inv);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) v[q] = cmul(v[q], sj);
+        for (int q = 0; q < 16; ++q) {
+          const int2 zi = unpack2(Z[own<T>(jbase, j, q)]);
+          v[q] = cmul(make_float2((float)zi.x, (float)zi.y), sjs);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int re = (int)(uint32_t)(Z[own<T>(jbase, j, q)] & 0xFFFFFFFFull);
+          v[q] = make_float2((float)re * inv, 0.0f);
+        }
       }
       Stage<L, 0>::run(v, P0, P1, tl, tm, j);
       if (side == 0) {
