@@ -7,7 +7,8 @@
 //   hs[side][t][x]        int32  (h(x) << 1) | (s(x) == -1)
 //   cnt[side][t][u]       int32  members of bucket u (u < b)
 //   pos[side][t][u]       int32  layout position of non-empty bucket u, -1 if empty
-//   ent[side][t][p]       uint32 bucket id at layout position p (bit 31 = padding)
+//   ent[side][t][p]       uint32 FFT fold entry of position p: (u div T) << 16 | fold_slot(u)
+//                                (0xFFFFFFFF = padding)
 //   tab[side][t][p]       uint32 first member | sign << 31 | more-members << 30
 //   SA[side][t][k][p]     float  count sketch of column k (side 0) / row k (side 1)
 //   colmax[side][t][k]    float  max |SA[side][t][k][.]| (fixed-point scale of the fold)
@@ -25,7 +26,7 @@
 #include <stdint.h>
 
 #define CMM_P61 0x1FFFFFFFFFFFFFFFull
-#define CMM_PAD_ENT 0x80000000u
+#define CMM_PAD_ENT 0xFFFFFFFFu
 #define CMM_PAD_TAB 0xFFFFFFFFu
 #define CMM_TAB_NEG 0x80000000u
 #define CMM_TAB_MORE 0x40000000u
@@ -33,7 +34,17 @@
 
 namespace cmm {
 
-constexpr int kMaxLog2C = 12;          // FFT row length C <= 4096
+// LDS index swizzle of the FFT kernel's C-point buffers: xor the low 4 bits
+// with bits 4..7 (a bijection on [0, C)).
+__host__ __device__ __forceinline__ int fft_swizzle(int i) { return i ^ ((i >> 4) & 15); }
+
+// Fold entry of bucket u for an FFT row of length C = 1 << log2c: the
+// swizzled LDS slot of u mod C and the weight index u >> log2(C/16).
+__host__ __device__ __forceinline__ uint32_t fold_entry(uint32_t u, int log2c) {
+  return ((u >> (log2c - 4)) << 16) | (uint32_t)fft_swizzle((int)(u & ((1u << log2c) - 1)));
+}
+
+constexpr int kMaxLog2C = 13;          // FFT row length C <= 8192
 constexpr int kTopkCap = 4096;         // candidates sorted by the final top-K pass
 constexpr int kMaxKPerBlock = 128;     // k per FFT block (float32 partial sums)
 

@@ -48,23 +48,32 @@ template <> struct Elem<2> {      // fp8 e4m3fn bits
   }
 };
 
-// grid.x = k-blocks; block = 256 threads; dynamic LDS = n floats.
+// grid.x = k-blocks; block = 512 threads; dynamic LDS = n floats.
+// Positions are handled four at a time (16-byte table reads and stores; the
+// layout's segments are multiples of 64 positions, so a group of four never
+// straddles two segments).  The per-column max |value| is kept per thread and
+// merged through an LDS integer max (float bits of non-negative values order
+// like the integers), one barrier per row.
+constexpr int kCsThreads = 512;
+
 template <int DT, bool VEC>
-__global__ __launch_bounds__(256) void k_countsketch(SideDesc sd, int d, int m, int W, int kblock) {
+__global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, int m, int W, int kblock) {
   extern __shared__ float row[];
-  __shared__ float red[4];
+  __shared__ uint32_t smax[2][64];
   typedef Elem<DT> E;
   const int tid = threadIdx.x;
   const int n = sd.n;
   const int k0 = blockIdx.x * kblock;
   const int k1 = min(m, k0 + kblock);
   const typename E::S* X = (const typename E::S*)sd.X;
-  for (int k = k0; k < k1; ++k) {
+  if (tid < 128) smax[tid >> 6][tid & 63] = 0u;
+  int par = 0;
+  for (int k = k0; k < k1; ++k, par ^= 1) {
     const typename E::S* xr = X + (int64_t)k * sd.ld;
     if (VEC) {
       const typename E::V4* xv = (const typename E::V4*)xr;
       const int n4 = n >> 2;
-      for (int q = tid; q < n4; q += 256) {
+      for (int q = tid; q < n4; q += kCsThreads) {
         float o[4];
         E::four(xv[q], o);
         if (sd.scale) {
@@ -73,50 +82,58 @@ __global__ __launch_bounds__(256) void k_countsketch(SideDesc sd, int d, int m, 
         }
         *(float4*)&row[4 * q] = make_float4(o[0], o[1], o[2], o[3]);
       }
-      for (int x = 4 * n4 + tid; x < n; x += 256)
+      for (int x = 4 * n4 + tid; x < n; x += kCsThreads)
         row[x] = E::one(xr[x]) * (sd.scale ? sd.scale[x] : 1.0f);
     } else {
-      for (int x = tid; x < n; x += 256)
+      for (int x = tid; x < n; x += kCsThreads)
         row[x] = E::one(xr[x]) * (sd.scale ? sd.scale[x] : 1.0f);
     }
     __syncthreads();
     for (int t = 0; t < d; ++t) {
       const int L = sd.lseg[t];
-      const int total = W * L;
+      const int L4 = L >> 2;
+      const int total4 = W * L4;
       const uint32_t* tab = sd.tab + (int64_t)t * sd.Lrow;
       float* out = sd.SA + ((int64_t)t * m + k) * sd.Lrow;
       float amax = 0.0f;
-      for (int idx = tid; idx < total; idx += 256) {
-        const int w = idx / L;
-        const int p = w * sd.Lcap + (idx - w * L);
-        const uint32_t e = tab[p];
-        float v = 0.0f;
-        if (e != CMM_PAD_TAB) {
-          v = row[e & CMM_TAB_IDX];
-          if (e & CMM_TAB_NEG) v = -v;
-          if (e & CMM_TAB_MORE) {
-            const int64_t tp = (int64_t)t * sd.Lrow + p;
-            const int c = sd.cntp[tp];
-            const int32_t* mem = sd.perm + (int64_t)t * n + sd.moff[tp];
-            const int32_t* hs = sd.hs + (int64_t)t * n;
-            for (int a = 1; a < c; ++a) {
-              const int x = mem[a];
-              const float y = row[x];
-              v += (hs[x] & 1) ? -y : y;
+      for (int idx = tid; idx < total4; idx += kCsThreads) {
+        const int w = idx / L4;
+        const int p = w * sd.Lcap + 4 * (idx - w * L4);
+        const uint4 e4 = *(const uint4*)&tab[p];
+        const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
+        float v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t e = ev[q];
+          float x = 0.0f;
+          if (e != CMM_PAD_TAB) {
+            x = row[e & CMM_TAB_IDX];
+            if (e & CMM_TAB_NEG) x = -x;
+            if (e & CMM_TAB_MORE) {
+              const int64_t tp = (int64_t)t * sd.Lrow + p + q;
+              const int c = sd.cntp[tp];
+              const int32_t* mem = sd.perm + (int64_t)t * n + sd.moff[tp];
+              const int32_t* hs = sd.hs + (int64_t)t * n;
+              for (int a = 1; a < c; ++a) {
+                const int xm = mem[a];
+                const float y = row[xm];
+                x += (hs[xm] & 1) ? -y : y;
+              }
             }
           }
+          v[q] = x;
+          amax = fmaxf(amax, fabsf(x));
         }
-        out[p] = v;
-        amax = fmaxf(amax, fabsf(v));
+        *(float4*)&out[p] = make_float4(v[0], v[1], v[2], v[3]);
       }
-      // block max of |v| -> colmax[t][k]
       for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
-      if ((tid & 63) == 0) red[tid >> 6] = amax;
-      __syncthreads();
-      if (tid == 0) sd.colmax[(int64_t)t * m + k] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-      __syncthreads();
+      if ((tid & 63) == 0) atomicMax(&smax[par][t], __float_as_uint(amax));   // d <= 63
     }
     __syncthreads();
+    if (tid < d) {
+      sd.colmax[(int64_t)tid * m + k] = __uint_as_float(smax[par][tid]);
+      smax[par][tid] = 0u;   // free for row k+2 (the next row uses the other half)
+    }
   }
 }
 
@@ -125,8 +142,8 @@ hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStr
   const bool vec = (sd.n % 4 == 0) && (sd.ld % 4 == 0) &&
                    ((uintptr_t)sd.X % (4 * esz) == 0) &&
                    (sd.scale == nullptr || (uintptr_t)sd.scale % 16 == 0);
-  // aim for ~2048 blocks
-  int kblock = (int)((int64_t)g.m / 2048);
+  // aim for ~1024 blocks
+  int kblock = (int)((int64_t)g.m / 1024);
   if (kblock < 1) kblock = 1;
   const int blocks = (g.m + kblock - 1) / kblock;
   const size_t lds = (size_t)sd.n * sizeof(float);
@@ -137,7 +154,7 @@ hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStr
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
       if (e_ != hipSuccess) return e_;                                                      \
     }                                                                                       \
-    hipLaunchKernelGGL((k_countsketch<DTV, VV>), dim3(blocks), dim3(256), lds, s, sd, g.d, g.m, \
+    hipLaunchKernelGGL((k_countsketch<DTV, VV>), dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, \
                        g.W, kblock);                                                        \
   } while (0)
   if (dtype == 0) { if (vec) CMM_CS(0, true); else CMM_CS(0, false); }

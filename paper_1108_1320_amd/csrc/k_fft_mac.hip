@@ -36,7 +36,7 @@ namespace cmm {
 // consecutive complex values stay rows (stage reads at j + T v are
 // conflict-free) and the stride-16 writes of the first radix-16 stage spread
 // over all banks.
-__device__ __forceinline__ int sw(int i) { return i ^ ((i >> 4) & 15); }
+__device__ __forceinline__ int sw(int i) { return fft_swizzle(i); }
 
 // LDS address of slot j + T q (the own positions of thread j).  For T a
 // multiple of 256 the swizzle leaves the T q part alone, so the address is
@@ -66,11 +66,14 @@ template <int L> struct FftShape {
   static constexpr int E = L % 4;
   static constexpr int S = L / 4 + (E ? 1 : 0);
   static constexpr int G = T < 64 ? T : 64;
-  static constexpr int U = L == 12 ? 16 : 8;     // fold entries fetched per lane at once
+  static constexpr int U = L == 12 ? 16 : (L == 13 ? 4 : 8);   // fold entries fetched per lane at once
+                                                 // (L = 13 has 8 waves, half the entries each)
   static constexpr int span(int s) { return s == 0 ? 1 : (E ? (1 << E) : 16) * ipow16(s - 1); }
   static constexpr int radix(int s) { return (s == 0 && E) ? (1 << E) : 16; }
-  // twiddle table of the middle stage 1 (present when S == 3)
-  static constexpr int NMID = S >= 3 ? 15 * ((E ? (1 << E) : 16)) : 0;
+  // twiddle tables of the middle stages 1 .. S-2, one after the other:
+  // stage s starts at tmoff(s) and holds 15 * span(s) entries
+  static constexpr int tmoff(int s) { return s <= 1 ? 0 : tmoff(s - 1) + 15 * span(s - 1); }
+  static constexpr int NMID = S >= 3 ? tmoff(S - 1) : 0;
 };
 
 template <int L, int s> struct Stage {
@@ -92,8 +95,9 @@ template <int L, int s> struct Stage {
         for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tl[r - 1]);
       } else {
         const int jm = j % Ns;
+        const float2* tms = tm + F::tmoff(s);
 #pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tm[(r - 1) * Ns + jm]);
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tms[(r - 1) * Ns + jm]);
       }
     }
 #pragma unroll
@@ -162,22 +166,33 @@ __device__ __forceinline__ int2 unpack2(unsigned long long p) {
   return make_int2(re, im);
 }
 
+// The batch is folded in groups of 4 entries: a group that lies wholly past
+// the segment is skipped by a wave-uniform test; inside a group there is no
+// per-entry branch (so the weight reads issue together) and an invalid
+// entry (padding) adds 0 to the calling thread's own first slot.
 template <int L, int G, int kU>
 __device__ __forceinline__ void fold(const Batch<kU>& bt, unsigned long long* Z, int f1, int m16,
-                                     const float2* w16, float scale) {
-  constexpr int C = 1 << L;
-  constexpr int LT = L - 4;          // log2 T
+                                     const float2* w16, float scale, int own_slot, int ls,
+                                     int first) {
+  static_assert(kU % 4 == 0, "groups of 4");
 #pragma unroll
-  for (int i = 0; i < kU; ++i) {
-    const uint32_t u = bt.u[i];
-    if ((int)u < 0) continue;        // padding or past the segment
-    unsigned long long* dst = &Z[sw((int)(u & (C - 1)))];
-    const float sv = bt.v[i] * scale;
-    if (f1 == 0) {
-      atomicAdd(dst, (unsigned long long)(long long)__float2int_rn(sv));
-    } else {
-      const float2 w = w16[(f1 * (int)(u >> LT)) & m16];
-      atomicAdd(dst, pack2(__float2int_rn(sv * w.x), __float2int_rn(sv * w.y)));
+  for (int g0 = 0; g0 < kU; g0 += 4) {
+    if ((first + g0) * G >= ls) break;
+    float2 w[4];
+    if (f1 != 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) w[i] = w16[(f1 * (int)(bt.u[g0 + i] >> 16)) & m16];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t e = bt.u[g0 + i];   // (u div T) << 16 | swizzled slot
+      const bool ok = e != 0xFFFFFFFFu;
+      const int slot = ok ? (int)(e & 0xFFFFu) : own_slot;
+      // |value * scale| < 2^30: float32 keeps 24 bits, so values near the top
+      // have no fraction and truncation only touches the smallest ones
+      const float sv = ok ? bt.v[g0 + i] * scale : 0.0f;
+      if (f1 == 0) atomicAdd(&Z[slot], (unsigned long long)(long long)(int)sv);
+      else atomicAdd(&Z[slot], pack2((int)(sv * w[i].x), (int)(sv * w[i].y)));
     }
   }
 }
@@ -191,7 +206,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   float2* P1 = lds + C;
   float2* tm = lds + 2 * C;
   float2* w16 = tm + F::NMID;        // omega_16R^x, x < 16 R
-  static_assert(F::S <= 3, "one middle stage at most");
+  static_assert(F::S <= 4, "at most two middle stages");
 
   const int bid = blockIdx.x;
   const int logical = a.remap ? (bid & 7) * (a.nwg >> 3) + (bid >> 3) : bid;
@@ -218,11 +233,12 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
     for (int r = 1; r < 16; ++r)
       tl[r - 1] = a.tw[(int64_t)((j % Ns) * r) * (C / (16 * Ns)) * R];
   }
-  if constexpr (F::NMID > 0) {
-    constexpr int Ns = F::span(1);
-    for (int e = j; e < F::NMID; e += T) {
+#pragma unroll
+  for (int s = 1; s < F::S - 1; ++s) {
+    const int Ns = F::span(s);
+    for (int e = j; e < 15 * Ns; e += T) {
       const int r = e / Ns + 1, jm = e % Ns;
-      tm[e] = a.tw[(int64_t)(jm * r) * (C / (16 * Ns)) * R];
+      tm[F::tmoff(s) + e] = a.tw[(int64_t)(jm * r) * (C / (16 * Ns)) * R];
     }
   }
   __syncthreads();
@@ -260,10 +276,10 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) Z[own<T>(jbase, j, q)] = 0ull;
       __builtin_amdgcn_wave_barrier();
-      fold<L, G, kU>(bt, Z, f1, m16, w16, scale);
+      fold<L, G, kU>(bt, Z, f1, m16, w16, scale, jbase, ls, 0);
       for (int first = kU; first * G < ls; first += kU) {
         fetch<G, kU>(bt, sa, en, ls, lane, first);
-        fold<L, G, kU>(bt, Z, f1, m16, w16, scale);
+        fold<L, G, kU>(bt, Z, f1, m16, w16, scale, jbase, ls, first);
       }
       // first batch of the next (side, k), in flight during the transform
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0);
@@ -336,6 +352,7 @@ hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc&
     case 10: return launch_L<10>(a, s);
     case 11: return launch_L<11>(a, s);
     case 12: return launch_L<12>(a, s);
+    case 13: return launch_L<13>(a, s);
     default: return hipErrorInvalidValue;
   }
 }

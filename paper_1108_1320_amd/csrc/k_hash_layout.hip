@@ -105,7 +105,7 @@ hipError_t launch_count(const Geometry& g, SideDesc& sd, hipStream_t s) {
 // One block per (segment w, repetition t): rank the non-empty buckets of the
 // segment in increasing u and give each its layout position.
 __global__ __launch_bounds__(1024) void k_segment_rank(const int32_t* __restrict__ cnt,
-                                                       int64_t b, int T, int G, int W, int Lcap,
+                                                       int64_t b, int log2c, int T, int G, int W, int Lcap,
                                                        int Lrow, int32_t* __restrict__ pos,
                                                        uint32_t* __restrict__ ent,
                                                        int32_t* __restrict__ cntp,
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(1024) void k_segment_rank(const int32_t* __restrict
     if (valid) {
       if (occ && rank < Lcap) {
         pos_t[u] = w * Lcap + rank;
-        ent_t[rank] = (uint32_t)u;
+        ent_t[rank] = fold_entry((uint32_t)u, log2c);
         cntp_t[rank] = c;
       } else {
         pos_t[u] = -1;
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(1024) void k_layout_finish(int W, int G, int Lcap, 
   for (int w = 0; w < W; ++w) {
     int sc = min(segcount[t * W + w], Lcap);
     for (int r = sc + tid; r < L; r += blockDim.x) {
-      ent_t[w * Lcap + r] = CMM_PAD_ENT | (uint32_t)(w * G);
+      ent_t[w * Lcap + r] = CMM_PAD_ENT;
       tab_t[w * Lcap + r] = CMM_PAD_TAB;
       cntp_t[w * Lcap + r] = 0;
     }
@@ -258,7 +258,7 @@ __global__ void k_build_tab(const int32_t* __restrict__ hs, int d, int n, int W,
 
 hipError_t launch_layout(const Geometry& g, SideDesc& sd, int32_t* overflow, hipStream_t s) {
   hipError_t e;
-  hipLaunchKernelGGL(k_segment_rank, dim3(g.W, g.d), dim3(1024), 0, s, sd.cnt, g.b, g.T, g.G,
+  hipLaunchKernelGGL(k_segment_rank, dim3(g.W, g.d), dim3(1024), 0, s, sd.cnt, g.b, g.log2c, g.T, g.G,
                      g.W, sd.Lcap, sd.Lrow, sd.pos, sd.ent, sd.cntp, sd.segcount, overflow);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_layout_finish, dim3(g.d), dim3(1024), 0, s, g.W, g.G, sd.Lcap, sd.Lrow,
