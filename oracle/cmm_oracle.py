@@ -205,6 +205,31 @@ def sketch_from_product(A: np.ndarray, B: np.ndarray, tables, b: int) -> np.ndar
     return bin_product(AB, tables, b)
 
 
+def sketch_buckets(A: np.ndarray, B: np.ndarray, tables, b: int, t: int, us,
+                   zero_diagonal: bool = False) -> np.ndarray:
+    """Selected entries c_t[u] of the definition, one bucket at a time: the
+    pairs (i, j) with (h1(i) + h2(j)) mod b = u are listed from h2's inverse,
+    and each (AB)_ij is the float64 dot product of row i of A and column j of
+    B.  ``zero_diagonal`` leaves out i = j (the sketch of AB with a zero
+    diagonal).  For products too large to form whole."""
+    h1, s1, h2, s2 = tables
+    order = np.argsort(h2[t], kind="stable")
+    hsorted = h2[t][order]
+    out = np.empty(len(us))
+    for q, u in enumerate(us):
+        need = (u - h1[t]) % b                      # h2(j) needed for each i
+        lo = np.searchsorted(hsorted, need, side="left")
+        hi = np.searchsorted(hsorted, need, side="right")
+        ii = np.repeat(np.arange(h1.shape[1]), hi - lo)
+        jj = order[np.concatenate([np.arange(a, z) for a, z in zip(lo, hi)])] if len(ii) else np.zeros(0, np.int64)
+        if zero_diagonal:
+            keep = ii != jj
+            ii, jj = ii[keep], jj[keep]
+        vals = np.einsum("pk,kp->p", A[ii, :], B[:, jj]) if len(ii) else np.zeros(0)
+        out[q] = float((s1[t, ii] * s2[t, jj] * vals).sum())
+    return out
+
+
 def subtract_diagonal(c: np.ndarray, diag: np.ndarray, tables, b: int) -> np.ndarray:
     """Sketch of AB with its diagonal zeroed (Section 3.2, Q-tilde): remove
     s1(i)s2(i)(AB)_ii from bucket h(i,i) of every repetition."""

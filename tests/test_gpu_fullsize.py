@@ -1,0 +1,150 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration
+bench.py times.
+
+* covariance n = m = 4096, float32, b = 2^16, d = 5: the whole sketch against
+  the oracle (float64 AB in seconds) and the top-64 over i < j.
+* DCT transform n = 8192, bf16, b = 2^17, d = 7, top-16 per column: sampled
+  sketch entries computed one bucket at a time, and the returned estimates of
+  sampled columns.
+* covariance n = m = 16384, fp8 e4m3fn with per-column scales, b = 2^18,
+  d = 9, top-256 over i < j: sampled sketch entries and sampled returned
+  estimates (the oracle cannot afford all 2.7e8 entries here).
+
+Tolerances as in test_gpu_parity: rel. L2 1e-5 on c per repetition (on
+samples: |dc| <= 1e-5 ||c_t||_2 / sqrt(b) * 10, i.e. within ten times the
+rms per-entry error the 1e-5 L2 budget allows), estimates within the max
+sketch error.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cmm_oracle as O
+import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(cmm):
+    c = cmm.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _product(cmm, ctx, w):
+    At = _dev(w.At_store)
+    B = At.clone() if w.same_operand else _dev(w.B_store)
+    sA = _dev(w.scaleA) if w.scaleA is not None else None
+    sB = _dev(w.scaleB) if w.scaleB is not None else None
+    return cmm.sketch_product(ctx, At, B, w.b, w.d, seed=w.seed, dtype=w.dtype, scaleA=sA,
+                              scaleB=sB, subtract_diag=w.subtract_diag, n1=w.n1, n3=w.n3, m=w.m)
+
+
+def test_cfg2_covariance_4096_f32(cmm, ctx):
+    _say("case: covariance n=m=4096 f32 b=2^16 d=5 (whole sketch)")
+    w = W.make_workload(2)
+    sk = _product(cmm, ctx, w)
+    c_gpu = sk.c()
+    A, B = W.dequantised(w)
+    c_ref, tabs, _ = O.run(A, B, w.b, w.d, w.seed, subtract_diag=True)
+    for t in range(w.d):
+        assert np.linalg.norm(c_gpu[t] - c_ref[t]) / np.linalg.norm(c_ref[t]) <= 1e-5
+    oi, oj, ov = sk.topk(w.K, "upper")
+    delta = 2 * (np.abs(c_gpu.astype(np.float32).astype(np.float64) - c_ref).max() + 1e-6 * np.abs(c_ref).max())
+    i, j = O.candidates("upper", w.n1, w.n3)
+    vals = O.decode(c_ref, tabs, i, j)
+    order = np.lexsort((i * w.n3 + j, -np.abs(vals)))
+    tau = abs(vals[order[w.K - 1]])
+    sure = {(int(i[o]), int(j[o])) for o in order[:w.K] if abs(vals[o]) > tau + delta}
+    got = set(zip(oi.tolist(), oj.tolist()))
+    assert sure <= got
+    assert np.abs(ov - O.decode(c_ref, tabs, oi, oj)).max() <= delta
+    assert all(abs(v) >= tau - delta for v in O.decode(c_ref, tabs, oi, oj))
+
+
+def _sampled_bucket_check(sk, A, B, w, per_rep, zero_diagonal, seed):
+    c_gpu = sk.c()
+    tabs = O.hash_tables(O.hash_params(w.seed, w.d), w.n1, w.n3, w.b)
+    g = np.random.default_rng(seed)
+    worst = 0.0
+    for t in range(w.d):
+        us = g.choice(w.b, per_rep, replace=False)
+        ref = O.sketch_buckets(A, B, tabs, w.b, t, us, zero_diagonal=zero_diagonal)
+        # per-entry budget: ten times the rms error a 1e-5 relative L2 error allows
+        budget = 10 * 1e-5 * np.linalg.norm(c_gpu[t]) / math.sqrt(w.b)
+        err = np.abs(c_gpu[t, us] - ref).max()
+        worst = max(worst, err / budget)
+        assert err <= budget, (t, err, budget)
+    return tabs, worst
+
+
+def test_cfg3_transform_8192_bf16(cmm, ctx):
+    _say("case: DCT transform n=8192 bf16 b=2^17 d=7 top-16 per column")
+    w = W.make_workload(3)
+    sk = _product(cmm, ctx, w)
+    A, B = W.dequantised(w)
+    A = np.ascontiguousarray(A)
+    tabs, worst = _sampled_bucket_check(sk, A, B, w, 24, False, 31)
+    _say(f"  sampled sketch error / budget: {worst:.3f}")
+    oi, oj, ov = sk.topk(w.K, "column")
+    g = np.random.default_rng(32)
+    cols = g.choice(w.n3, 3, replace=False)
+    c_gpu = sk.c()
+    for jj in cols:
+        rows = oi[jj * w.K:(jj + 1) * w.K]
+        vals = ov[jj * w.K:(jj + 1) * w.K]
+        assert len(set(rows.tolist())) == w.K
+        assert np.all(np.diff(np.abs(vals)) <= 1e-6 * abs(vals[0]))
+        # the returned values are the estimates decoded from the sketch entries
+        # the oracle computes one bucket at a time
+        for r, v in zip(rows[:4], vals[:4]):
+            xs = []
+            for t in range(w.d):
+                u = (tabs[0][t, r] + tabs[2][t, jj]) % w.b
+                cu = O.sketch_buckets(A, B, tabs, w.b, t, [u])[0]
+                xs.append(tabs[1][t, r] * tabs[3][t, jj] * cu)
+            ref = O.median(np.array(xs)[:, None], 0)[0]
+            tol = 1e-5 * np.abs(c_gpu).max() + 1e-6 * abs(ref)
+            assert abs(v - ref) <= tol, (jj, r, v, ref)
+    # recall of the planted spikes (reported, not asserted: the paper gives no figure)
+    hits = sum(len(set(oi[j * w.K:(j + 1) * w.K].tolist()) & set(w.planted[j].tolist())) for j in range(w.n3))
+    _say(f"  spike recall in the per-column top-16: {hits / (w.n3 * w.K):.4f}")
+
+
+def test_cfg4_covariance_16384_fp8(cmm, ctx):
+    _say("case: covariance n=m=16384 fp8 b=2^18 d=9 top-256 (sampled)")
+    w = W.make_workload(4)
+    sk = _product(cmm, ctx, w)
+    At_deq = W.dequantised(w)[1]               # X (m x n) as the GPU reads it
+    A = np.ascontiguousarray(At_deq.T)         # rows i of A = X^T, contiguous
+    tabs, worst = _sampled_bucket_check(sk, A, At_deq, w, 3, True, 41)
+    _say(f"  sampled sketch error / budget: {worst:.3f}")
+    oi, oj, ov = sk.topk(w.K, "upper")
+    assert len(set(zip(oi.tolist(), oj.tolist()))) == w.K and np.all(oi < oj)
+    assert np.all(np.diff(np.abs(ov)) <= 1e-6 * abs(ov[0]))
+    c_gpu = sk.c()
+    for q in (0, w.K // 2, w.K - 1):
+        i, j = int(oi[q]), int(oj[q])
+        xs = []
+        for t in range(w.d):
+            u = (tabs[0][t, i] + tabs[2][t, j]) % w.b
+            cu = O.sketch_buckets(A, At_deq, tabs, w.b, t, [u], zero_diagonal=True)[0]
+            xs.append(tabs[1][t, i] * tabs[3][t, j] * cu)
+        ref = O.median(np.array(xs)[:, None], 0)[0]
+        assert abs(ov[q] - ref) <= 1e-5 * np.abs(c_gpu).max() + 1e-6 * abs(ref), (q, ov[q], ref)
+    got = {(int(a), int(b)) for a, b in zip(oi, oj)}
+    want = {(int(min(p, q)), int(max(p, q))) for p, q in w.planted}
+    _say(f"  planted-pair recall in the top-256: {len(got & want) / len(want):.4f}")

@@ -302,3 +302,19 @@ def test_theorem6_tail_bound():
     err_f = float((mags[b // 20:] ** 2).sum())
     bound = 12 * math.sqrt(err_f / b)
     assert np.abs(C - AB).max() < bound
+
+
+def test_sketch_buckets_matches_definition():
+    """One-bucket-at-a-time evaluation equals the binned definition, with and
+    without the diagonal."""
+    g = np.random.default_rng(9)
+    A = g.standard_normal((37, 11)); B = g.standard_normal((11, 37))
+    tabs = O.hash_tables(O.hash_params(41, 2), 37, 37, 32)
+    full = O.sketch_from_product(A, B, tabs, 32)
+    AB = A @ B
+    zeroed = O.bin_product(AB - np.diag(np.diag(AB)), tabs, 32)
+    us = [0, 5, 17, 31]
+    for t in range(2):
+        np.testing.assert_allclose(O.sketch_buckets(A, B, tabs, 32, t, us), full[t, us], atol=1e-12)
+        np.testing.assert_allclose(O.sketch_buckets(A, B, tabs, 32, t, us, zero_diagonal=True),
+                                   zeroed[t, us], atol=1e-12)
