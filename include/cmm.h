@@ -63,6 +63,7 @@ extern "C" {
 /* flags of cmm_sketch_product_ex */
 #define CMM_SUBTRACT_DIAG 1u /* sketch AB with its diagonal zeroed (n1 == n3) */
 #define CMM_ASYNC         2u /* do not wait for the stream before returning */
+#define CMM_AUTOTUNE      4u /* cmm_batch_create: tune size classes not yet tuned */
 
 /* candidate domains of cmm_topk */
 #define CMM_TOPK_ALL        0 /* every (i, j) */
@@ -71,6 +72,26 @@ extern "C" {
 
 typedef struct cmm_ctx cmm_ctx;
 typedef struct cmm_sketch cmm_sketch;
+typedef struct cmm_batch cmm_batch;
+
+/* One product of a batch: the arguments of cmm_sketch_product_ex with a
+ * seed (A, B device pointers in the layouts above; flags 0 or
+ * CMM_SUBTRACT_DIAG). */
+typedef struct cmm_problem {
+  const void* A;
+  int64_t lda;
+  const void* B;
+  int64_t ldb;
+  int64_t n1, m, n3;
+  int64_t b;
+  int32_t d;
+  int32_t dtype;
+  const float* scaleA;
+  const float* scaleB;
+  uint64_t seed;
+  uint32_t flags;
+  uint32_t reserved;   /* must be 0 */
+} cmm_problem;
 
 /* ---- context ---------------------------------------------------------- */
 
@@ -91,7 +112,9 @@ const char* cmm_last_error(const cmm_ctx* ctx);
 /* Kernel timing: while enabled, the library records a pair of HIP events on
  * the context stream around every launch of the named kernels and sums
  * their durations.  `name` is one of "hash", "layout", "countsketch",
- * "fft_mac", "ifft", "decode".  Reading waits for the stream. */
+ * "fft_mac", "ifft", "decode", or "batch" (a whole graph replay of
+ * cmm_batch_run; the kernels inside a graph are not timed one by one).
+ * Reading waits for the stream. */
 int cmm_ctx_profile(cmm_ctx* ctx, int enable);
 int cmm_ctx_profile_read(cmm_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
 
@@ -151,6 +174,69 @@ int cmm_sketch_hashes(const cmm_sketch* sk, int32_t t, int32_t* h1, int8_t* s1,
  * not match. */
 int cmm_sketch_subtract_diagonal(cmm_sketch* sk, const double* diag, int64_t len);
 int cmm_sketch_merge(cmm_sketch* dst, const cmm_sketch* src);
+
+/* ---- many products in one launch --------------------------------------- */
+
+/* A batch is a set of independent sketch products (COMPRESSEDPRODUCT,
+ * Figure 1, once per problem, each with its own n1, m, n3, b, d, dtype and
+ * seed) recorded once into one HIP graph.  Creation validates every problem,
+ * computes each problem's bucket layout from its hash functions (which fix
+ * it), allocates the sketches and a workspace per concurrent branch of the
+ * graph (problems are spread over up to four branches, longest first), and
+ * captures every kernel of every product; it runs nothing but the layout
+ * pass.  The operand pointers are recorded: each replay reads the current
+ * contents of the same buffers, which must stay allocated while the batch
+ * lives.  With CMM_AUTOTUNE, size classes the context has no tuning for are
+ * tuned first (cmm_autotune).  count in [1, 4096]. */
+int cmm_batch_create(cmm_ctx* ctx, const cmm_problem* probs, int32_t count, uint32_t flags,
+                     cmm_batch** out);
+
+/* Replay the whole batch as one graph launch on the context stream; waits
+ * for it unless flags has CMM_ASYNC.  Replays of one batch are ordered on
+ * that stream and give identical sketches for identical operands. */
+int cmm_batch_run(cmm_batch* batch, uint32_t flags);
+
+/* The sketch of problem `index`, owned by the batch and rewritten by every
+ * replay; cmm_sketch_free() on it returns CMM_ESTATE. */
+int cmm_batch_sketch(cmm_batch* batch, int32_t index, cmm_sketch** out);
+
+/* Wait for the context stream and release the graph, the workspace and the
+ * batch's sketches. */
+int cmm_batch_free(cmm_batch* batch);
+
+/* One-shot form: create a batch of `count` problems, run it once, hand the
+ * sketches to the caller (outs[count], each freed with cmm_sketch_free()) and
+ * release the rest. */
+int cmm_sketch_product_batched(cmm_ctx* ctx, const cmm_problem* probs, int32_t count,
+                               cmm_sketch** outs);
+
+/* ---- tuning ------------------------------------------------------------ */
+
+/* The geometry of a product is (log2c, kmax, cs_blocks): the FFT row length
+ * C = 2^log2c of the four-step transform of length b = R*C (log2c in
+ * [4, 13], capped at log2 b), the largest number of k per spectral block
+ * (kmax in [1, 128]) and the number of count-sketch blocks over k
+ * (cs_blocks >= 1).  Tuning entries are keyed by size class: log2 b, the
+ * ceilings of log2 n1, log2 m, log2 n3, d and dtype.
+ *
+ * cmm_autotune times every candidate geometry of the class of (n1, m, n3,
+ * b, d, dtype) on synthetic operands on the context stream, stores the
+ * fastest for the class and returns it (tuning[3], may be NULL) with its
+ * time (best_ms, may be NULL).  Products whose class has an entry use it;
+ * others use the built-in default.  cmm_tuning_get returns the geometry a
+ * product of these sizes would use; cmm_tuning_set stores one.  Save/load
+ * write and read the entries as a JSON array (one object per class, tagged
+ * with the device's architecture name; entries of another architecture are
+ * skipped on load).  cmm_ctx_create loads the file named by the environment
+ * variable CMM_TUNE_CACHE when it is set and exists. */
+int cmm_autotune(cmm_ctx* ctx, int64_t n1, int64_t m, int64_t n3, int64_t b, int32_t d,
+                 int32_t dtype, int32_t* tuning, double* best_ms);
+int cmm_tuning_get(const cmm_ctx* ctx, int64_t n1, int64_t m, int64_t n3, int64_t b, int32_t d,
+                   int32_t dtype, int32_t* tuning);
+int cmm_tuning_set(cmm_ctx* ctx, int64_t n1, int64_t m, int64_t n3, int64_t b, int32_t d,
+                   int32_t dtype, const int32_t* tuning);
+int cmm_tuning_save(const cmm_ctx* ctx, const char* path);
+int cmm_tuning_load(cmm_ctx* ctx, const char* path);
 
 /* ---- decoding (DECOMPRESS, Figure 1) ---------------------------------- */
 

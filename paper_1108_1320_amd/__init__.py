@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libcmm.so")
 
 CMM_OK, CMM_EINVAL, CMM_ENOMEM, CMM_EHIP, CMM_EUNSUPPORTED, CMM_ESTATE = 0, -1, -2, -3, -4, -5
 CMM_F32, CMM_BF16, CMM_FP8_E4M3 = 0, 1, 2
-CMM_SUBTRACT_DIAG, CMM_ASYNC = 1, 2
+CMM_SUBTRACT_DIAG, CMM_ASYNC, CMM_AUTOTUNE = 1, 2, 4
 CMM_TOPK_ALL, CMM_TOPK_UPPER, CMM_TOPK_PER_COLUMN = 0, 1, 2
 DTYPES = {"f32": CMM_F32, "bf16": CMM_BF16, "fp8": CMM_FP8_E4M3}
 MODES = {"all": CMM_TOPK_ALL, "upper": CMM_TOPK_UPPER, "column": CMM_TOPK_PER_COLUMN}
@@ -32,6 +32,17 @@ _I64 = C.c_int64
 _I32 = C.c_int32
 _U32 = C.c_uint32
 _U64 = C.c_uint64
+
+
+class cmm_problem(C.Structure):
+    """One product of a batch (the C struct of the same name)."""
+    _fields_ = [("A", _P), ("lda", _I64), ("B", _P), ("ldb", _I64), ("n1", _I64), ("m", _I64),
+                ("n3", _I64), ("b", _I64), ("d", _I32), ("dtype", _I32), ("scaleA", _P),
+                ("scaleB", _P), ("seed", _U64), ("flags", _U32), ("reserved", _U32)]
+
+
+_PROB = C.POINTER(cmm_problem)
+_I32P = C.POINTER(_I32)
 
 _SIGS = {
     "cmm_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
@@ -57,6 +68,17 @@ _SIGS = {
     "cmm_estimate": (C.c_int, [_P, _I64, _I64, C.POINTER(C.c_double)]),
     "cmm_estimate_batch": (C.c_int, [_P, _P, _P, _I64, _P]),
     "cmm_topk": (C.c_int, [_P, _I32, _I32, _P, _P, _P]),
+    "cmm_batch_create": (C.c_int, [_P, _PROB, _I32, _U32, C.POINTER(_P)]),
+    "cmm_batch_run": (C.c_int, [_P, _U32]),
+    "cmm_batch_sketch": (C.c_int, [_P, _I32, C.POINTER(_P)]),
+    "cmm_batch_free": (C.c_int, [_P]),
+    "cmm_sketch_product_batched": (C.c_int, [_P, _PROB, _I32, C.POINTER(_P)]),
+    "cmm_autotune": (C.c_int, [_P, _I64, _I64, _I64, _I64, _I32, _I32, _I32P,
+                               C.POINTER(C.c_double)]),
+    "cmm_tuning_get": (C.c_int, [_P, _I64, _I64, _I64, _I64, _I32, _I32, _I32P]),
+    "cmm_tuning_set": (C.c_int, [_P, _I64, _I64, _I64, _I64, _I32, _I32, _I32P]),
+    "cmm_tuning_save": (C.c_int, [_P, C.c_char_p]),
+    "cmm_tuning_load": (C.c_int, [_P, C.c_char_p]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -231,6 +253,66 @@ def cmm_topk(sk, K: int, mode: int):
     return oi, oj, ov
 
 
+def _problems(probs):
+    arr = (cmm_problem * len(probs))()
+    for q, p in enumerate(probs):
+        arr[q] = p
+    return arr
+
+
+def cmm_batch_create(ctx, probs, flags=0):
+    out = _P()
+    arr = _problems(probs)
+    _check(load().cmm_batch_create(ctx, arr, len(probs), flags, C.byref(out)), "cmm_batch_create", ctx)
+    return out
+
+
+def cmm_batch_run(batch, flags=0, ctx=None):
+    _check(load().cmm_batch_run(batch, flags), "cmm_batch_run", ctx)
+
+
+def cmm_batch_sketch(batch, index: int):
+    out = _P()
+    _check(load().cmm_batch_sketch(batch, index, C.byref(out)), "cmm_batch_sketch")
+    return out
+
+
+def cmm_batch_free(batch):
+    _check(load().cmm_batch_free(batch), "cmm_batch_free")
+
+
+def cmm_sketch_product_batched(ctx, probs):
+    outs = (_P * len(probs))()
+    arr = _problems(probs)
+    _check(load().cmm_sketch_product_batched(ctx, arr, len(probs), outs), "cmm_sketch_product_batched", ctx)
+    return [_P(h) for h in outs]
+
+
+def cmm_autotune(ctx, n1, m, n3, b, d, dtype):
+    t = (_I32 * 3)(); ms = C.c_double()
+    _check(load().cmm_autotune(ctx, n1, m, n3, b, d, dtype, t, C.byref(ms)), "cmm_autotune", ctx)
+    return (t[0], t[1], t[2]), ms.value
+
+
+def cmm_tuning_get(ctx, n1, m, n3, b, d, dtype):
+    t = (_I32 * 3)()
+    _check(load().cmm_tuning_get(ctx, n1, m, n3, b, d, dtype, t), "cmm_tuning_get", ctx)
+    return (t[0], t[1], t[2])
+
+
+def cmm_tuning_set(ctx, n1, m, n3, b, d, dtype, tuning):
+    t = (_I32 * 3)(*tuning)
+    _check(load().cmm_tuning_set(ctx, n1, m, n3, b, d, dtype, t), "cmm_tuning_set", ctx)
+
+
+def cmm_tuning_save(ctx, path: str):
+    _check(load().cmm_tuning_save(ctx, path.encode()), "cmm_tuning_save", ctx)
+
+
+def cmm_tuning_load(ctx, path: str):
+    _check(load().cmm_tuning_load(ctx, path.encode()), "cmm_tuning_load", ctx)
+
+
 # ------------------------------------------------------------- object layer
 
 class Context:
@@ -256,18 +338,35 @@ class Context:
     def profile_read(self, name: str):
         return cmm_ctx_profile_read(self.handle, name)
 
+    def autotune(self, n1, m, n3, b, d, dtype="f32"):
+        """Tune the size class of these sizes; returns ((log2c, kmax, cs_blocks), ms)."""
+        return cmm_autotune(self.handle, n1, m, n3, b, d, DTYPES[dtype])
+
+    def tuning(self, n1, m, n3, b, d, dtype="f32"):
+        return cmm_tuning_get(self.handle, n1, m, n3, b, d, DTYPES[dtype])
+
+    def set_tuning(self, n1, m, n3, b, d, dtype, tuning):
+        cmm_tuning_set(self.handle, n1, m, n3, b, d, DTYPES[dtype], tuning)
+
+    def save_tuning(self, path):
+        cmm_tuning_save(self.handle, path)
+
+    def load_tuning(self, path):
+        cmm_tuning_load(self.handle, path)
+
 
 class Sketch:
     """Owning wrapper of a cmm_sketch handle."""
 
-    def __init__(self, handle, ctx: Context):
+    def __init__(self, handle, ctx: Context, owner=None):
         self.handle = handle
-        self.ctx = ctx   # keeps the context alive
+        self.ctx = ctx       # keeps the context alive
+        self.owner = owner   # a Batch that owns the handle, else None
 
     def free(self):
-        if self.handle:
+        if self.handle and self.owner is None:
             cmm_sketch_free(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -326,3 +425,49 @@ def sketch_product_tables(ctx: Context, At, B, b, h1, s1, h2, s2, dtype="f32") -
                                   At.shape[0], B.shape[1], DTYPES[dtype], None, None, b, d,
                                   h1, s1, h2, s2)
     return Sketch(h, ctx)
+
+
+def problem(At, B, b: int, d: int, seed: int = 0, dtype: str = "f32", scaleA=None, scaleB=None,
+            subtract_diag: bool = False, n1: int | None = None, n3: int | None = None,
+            m: int | None = None) -> cmm_problem:
+    """A cmm_problem over the k-major device arrays At (m x lda) and B (m x ldb),
+    as in sketch_product.  The tensors must outlive every batch built on it."""
+    return cmm_problem(
+        A=At.data_ptr(), lda=At.stride(0), B=B.data_ptr(), ldb=B.stride(0),
+        n1=n1 if n1 is not None else At.shape[1], m=m if m is not None else At.shape[0],
+        n3=n3 if n3 is not None else B.shape[1], b=b, d=d, dtype=DTYPES[dtype],
+        scaleA=None if scaleA is None else scaleA.data_ptr(),
+        scaleB=None if scaleB is None else scaleB.data_ptr(), seed=seed,
+        flags=CMM_SUBTRACT_DIAG if subtract_diag else 0, reserved=0)
+
+
+class Batch:
+    """Owning wrapper of a cmm_batch: products recorded into one HIP graph."""
+
+    def __init__(self, ctx: Context, probs, autotune: bool = False, keep=None):
+        self.ctx = ctx
+        self.keep = keep   # e.g. the operand tensors, kept alive with the batch
+        self.count = len(probs)
+        self.handle = cmm_batch_create(ctx.handle, probs, CMM_AUTOTUNE if autotune else 0)
+
+    def run(self, asynchronous: bool = False):
+        cmm_batch_run(self.handle, CMM_ASYNC if asynchronous else 0, self.ctx.handle)
+
+    def sketch(self, index: int) -> Sketch:
+        return Sketch(cmm_batch_sketch(self.handle, index), self.ctx, owner=self)
+
+    def free(self):
+        if self.handle:
+            cmm_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def sketch_product_batched(ctx: Context, probs) -> list:
+    """Every product of `probs` in one graph launch; returns owned Sketches."""
+    return [Sketch(h, ctx) for h in cmm_sketch_product_batched(ctx.handle, probs)]

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -16,11 +17,25 @@ namespace {
 
 constexpr uint32_t kCtxMagic = 0xC3A70001u;
 constexpr uint32_t kSketchMagic = 0xC3A75001u;
+constexpr uint32_t kBatchMagic = 0xC3A7B001u;
 constexpr uint32_t kDeadMagic = 0xDEADDEADu;
 
 struct Pending {
   std::string name;
   hipEvent_t a, b;
+};
+
+// Tuning key of a product: sizes rounded to powers of two.
+struct TuneKey {
+  int log2b, ln1, lm, ln3, d, dtype;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(log2b, ln1, lm, ln3, d, dtype) < std::tie(o.log2b, o.ln1, o.lm, o.ln3, o.d, o.dtype);
+  }
+};
+
+struct TuneEntry {
+  cmm::Tuning tu;
+  double ms = 0.0;
 };
 
 }  // namespace
@@ -37,6 +52,8 @@ struct cmm_ctx {
   std::vector<Pending> pending;
   std::map<std::string, std::pair<double, int64_t>> prof_acc;
   uint32_t* pinned_u32 = nullptr;   // small pinned host scratch
+  std::map<TuneKey, TuneEntry> tuning;
+  std::string arch;
 };
 
 struct cmm_sketch {
@@ -51,6 +68,7 @@ struct cmm_sketch {
   int32_t* hs2 = nullptr;
   double* c64 = nullptr;
   float* c32 = nullptr;
+  cmm_batch* owner = nullptr;     // set while the sketch belongs to a batch
 };
 
 namespace {
@@ -166,14 +184,23 @@ int get_twiddles(cmm_ctx* c, int64_t b, double2** t64, float2** t32) {
   return CMM_OK;
 }
 
-cmm::Geometry make_geometry(int64_t b, int d, int64_t m) {
+cmm::Tuning default_tuning(int64_t b) {
+  cmm::Tuning t;
+  // 4096-point rows measured fastest on b = 2^16 (8192-point rows: fewer
+  // rows but one block per CU); CMM_LOG2C overrides for experiments
+  t.log2c = 12;
+  if (const char* ev = std::getenv("CMM_LOG2C")) t.log2c = std::atoi(ev);
+  t.log2c = std::max(4, std::min(cmm::kMaxLog2C, t.log2c));
+  (void)b;
+  return t;
+}
+
+cmm::Geometry make_geometry(int64_t b, int d, int64_t m, const cmm::Tuning& tu) {
   cmm::Geometry g;
   g.b = b; g.log2b = ilog2(b); g.d = d; g.m = (int)m;
-  // FFT row length: 4096 measured fastest on the b = 2^16 covariance product;
-  // 8192 (fewer rows, one block per CU) is kept for tuning (CMM_LOG2C).
-  int lc = 12;
-  if (const char* ev = std::getenv("CMM_LOG2C")) lc = std::max(4, std::min(cmm::kMaxLog2C, std::atoi(ev)));
-  g.log2c = std::min(g.log2b, lc);
+  // at most 256 rows (R = b / C): the fold-weight table of 16 R entries
+  // stays in LDS and a bucket's row index fits the 16-bit field of its entry
+  g.log2c = std::min(g.log2b, std::max(tu.log2c, g.log2b - 8));
   const int C = 1 << g.log2c;
   g.T = C / 16;
   g.G = std::min(g.T, 64);
@@ -181,13 +208,18 @@ cmm::Geometry make_geometry(int64_t b, int d, int64_t m) {
   g.R = (int)(b / C);
   g.rows = g.R > 1 ? g.R / 2 + 1 : 1;
   const int64_t base = (int64_t)d * g.rows;
+  const int kmax = std::max(1, std::min(tu.kmax, cmm::kMaxKPerBlock));
   int64_t ks = std::max<int64_t>(1, (2048 + base - 1) / base);
-  ks = std::max<int64_t>(ks, (m + cmm::kMaxKPerBlock - 1) / cmm::kMaxKPerBlock);
+  ks = std::max<int64_t>(ks, (m + kmax - 1) / kmax);
   ks = std::min<int64_t>(ks, m);
   while (ks < m && (base * ks) % 8 != 0) ++ks;
   g.KS = (int)std::max<int64_t>(1, ks);
+  g.cs_blocks = std::max(1, tu.cs_blocks);
   return g;
 }
+
+cmm::Tuning lookup_tuning(const cmm_ctx* c, int64_t n1, int64_t m, int64_t n3, int64_t b, int d,
+                          int dtype);
 
 // Upper bound on the non-empty buckets of one layout segment.
 int layout_cap(int64_t n, int64_t b, int W, bool safe) {
@@ -198,6 +230,70 @@ int layout_cap(int64_t n, int64_t b, int W, bool safe) {
   int64_t cap = (int64_t)std::ceil(mu + 8.0 * std::sqrt(mu) + 64.0);
   cap = std::min<int64_t>(cap, hard);
   return (int)((cap + 63) & ~63LL);
+}
+
+// Element counts of every workspace buffer of one product.
+enum WsBuf { W_CNT0, W_POS0, W_ENT0, W_TAB0, W_CNTP0, W_MOFF0, W_FILL0, W_PERM0, W_SEG0, W_LSEG0,
+             W_SA0, W_CMAX0, W_CNT1, W_POS1, W_ENT1, W_TAB1, W_CNTP1, W_MOFF1, W_FILL1, W_PERM1,
+             W_SEG1, W_LSEG1, W_SA1, W_CMAX1, W_PPART, W_WORK0, W_WORK1, W_OFLOW, W_PARTIAL,
+             W_DIAG, W_COUNT };
+constexpr size_t kElemSize[W_COUNT] = {4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4,
+                                       4, 4, 4, 4, 8, 16, 16, 4, 8, 8};
+
+struct WsSpec {
+  size_t count[W_COUNT] = {};
+  int Lcap[2] = {0, 0};
+  int kch = 1;
+};
+
+WsSpec ws_spec(const cmm::Geometry& g, int64_t n1, int64_t n3, bool safe, uint32_t flags) {
+  WsSpec w;
+  const int64_t nn[2] = {n1, n3};
+  for (int q = 0; q < 2; ++q) {
+    const int o = q * (W_CNT1 - W_CNT0);
+    w.Lcap[q] = layout_cap(nn[q], g.b, g.W, safe);
+    const size_t Lrow = (size_t)g.W * w.Lcap[q];
+    w.count[W_CNT0 + o] = (size_t)g.d * g.b;
+    w.count[W_POS0 + o] = (size_t)g.d * g.b;
+    w.count[W_ENT0 + o] = w.count[W_TAB0 + o] = w.count[W_CNTP0 + o] = (size_t)g.d * Lrow;
+    w.count[W_MOFF0 + o] = w.count[W_FILL0 + o] = (size_t)g.d * Lrow;
+    w.count[W_PERM0 + o] = (size_t)g.d * nn[q];
+    w.count[W_SEG0 + o] = (size_t)g.d * g.W;
+    w.count[W_LSEG0 + o] = (size_t)g.d;
+    w.count[W_SA0 + o] = (size_t)g.d * g.m * Lrow;
+    w.count[W_CMAX0 + o] = (size_t)g.d * g.m;
+  }
+  w.count[W_PPART] = (size_t)g.d * g.KS * g.rows * ((size_t)1 << g.log2c);
+  w.count[W_WORK0] = w.count[W_WORK1] = (size_t)g.d * g.b;
+  w.count[W_OFLOW] = 1;
+  if (flags & CMM_SUBTRACT_DIAG) {
+    const int n = (int)n1;
+    w.kch = (int)std::max<int64_t>(1, std::min<int64_t>(g.m, 1 + 4096 / ((n + 255) / 256)));
+    w.count[W_PARTIAL] = (size_t)w.kch * n;
+    w.count[W_DIAG] = (size_t)n;
+  }
+  return w;
+}
+
+struct WsPtrs {
+  void* p[W_COUNT] = {};
+};
+
+// Allocate every buffer of `spec` (sizes only) from the context cache.
+int ws_alloc(cmm_ctx* c, const WsSpec& spec, WsPtrs& ptr, std::vector<void*>& owned) {
+  for (int i = 0; i < W_COUNT; ++i) {
+    if (spec.count[i] == 0) continue;
+    void* q = dalloc(c, spec.count[i] * kElemSize[i]);
+    if (!q) return fail(c, CMM_ENOMEM, "workspace allocation failed");
+    owned.push_back(q);
+    ptr.p[i] = q;
+  }
+  return CMM_OK;
+}
+
+void ws_release(cmm_ctx* c, std::vector<void*>& owned) {
+  for (void* q : owned) dfree(c, q);
+  owned.clear();
 }
 
 struct Work {
@@ -227,97 +323,147 @@ int check_operands(cmm_ctx* c, const void* A, int64_t lda, const void* B, int64_
   return CMM_OK;
 }
 
-int run_product(cmm_ctx* c, cmm_sketch* sk, const void* A, int64_t lda, const void* B, int64_t ldb,
-                int32_t dtype, const float* scaleA, const float* scaleB, uint32_t flags,
-                bool safe_layout, bool* overflowed) {
-  hipStream_t s = c->stream;
-  cmm::Geometry g = make_geometry(sk->b, sk->d, sk->m);
-  const int C = 1 << g.log2c;
-  Work w(c);
-  cmm::SideDesc side[2];
-  const int64_t nn[2] = {sk->n1, sk->n3};
-  const void* X[2] = {A, B};
-  const int64_t ld[2] = {lda, ldb};
-  const float* sc[2] = {scaleA, scaleB};
-  int32_t* hsv[2] = {sk->hs1, sk->hs2};
-  const bool async = flags & CMM_ASYNC;
-  for (int q = 0; q < 2; ++q) {
-    cmm::SideDesc& sd = side[q];
-    sd.X = X[q]; sd.ld = ld[q]; sd.scale = sc[q]; sd.n = (int)nn[q];
-    sd.hs = hsv[q];
-    sd.Lcap = layout_cap(nn[q], g.b, g.W, safe_layout || async);
-    sd.Lrow = g.W * sd.Lcap;
-    sd.cnt = w.get<int32_t>((size_t)g.d * g.b);
-    sd.pos = w.get<int32_t>((size_t)g.d * g.b);
-    sd.ent = w.get<uint32_t>((size_t)g.d * sd.Lrow);
-    sd.tab = w.get<uint32_t>((size_t)g.d * sd.Lrow);
-    sd.cntp = w.get<int32_t>((size_t)g.d * sd.Lrow);
-    sd.moff = w.get<int32_t>((size_t)g.d * sd.Lrow);
-    sd.fill = w.get<int32_t>((size_t)g.d * sd.Lrow);
-    sd.perm = w.get<int32_t>((size_t)g.d * sd.n);
-    sd.segcount = w.get<int32_t>((size_t)g.d * g.W);
-    sd.lseg = w.get<int32_t>((size_t)g.d);
-    sd.SA = w.get<float>((size_t)g.d * g.m * sd.Lrow);
-    sd.colmax = w.get<float>((size_t)g.d * g.m);
-    if (!sd.colmax || !sd.cnt || !sd.pos || !sd.ent || !sd.tab || !sd.cntp || !sd.moff || !sd.fill || !sd.perm ||
-        !sd.segcount || !sd.lseg || !sd.SA)
-      return fail(c, CMM_ENOMEM, "workspace allocation failed");
-  }
-  float2* Ppart = w.get<float2>((size_t)g.d * g.KS * g.rows * C);
-  double2* work0 = w.get<double2>((size_t)g.d * g.b);
-  double2* work1 = w.get<double2>((size_t)g.d * g.b);
-  int32_t* oflow = w.get<int32_t>(1);
-  uint64_t* pdev = sk->has_params ? w.get<uint64_t>((size_t)g.d * 8) : nullptr;
-  if (!Ppart || !work0 || !work1 || !oflow || (sk->has_params && !pdev))
-    return fail(c, CMM_ENOMEM, "workspace allocation failed");
-  double2* tw64; float2* tw32;
-  int rc = get_twiddles(c, g.b, &tw64, &tw32);
-  if (rc) return rc;
+struct Operands {
+  const void* A; int64_t lda; const void* B; int64_t ldb;
+  int32_t dtype; const float* scaleA; const float* scaleB; uint32_t flags;
+};
 
+// Side descriptors of a product over the buffers `ptr` (which may be larger
+// than this product needs, e.g. a workspace shared by a batch).
+void bind_sides(const cmm::Geometry& g, const cmm_sketch* sk, const Operands& op,
+                const WsSpec& spec, const WsPtrs& ptr, cmm::SideDesc side[2]) {
+  const int64_t nn[2] = {sk->n1, sk->n3};
+  const void* X[2] = {op.A, op.B};
+  const int64_t ld[2] = {op.lda, op.ldb};
+  const float* sc[2] = {op.scaleA, op.scaleB};
+  int32_t* hsv[2] = {sk->hs1, sk->hs2};
+  for (int q = 0; q < 2; ++q) {
+    const int o = q * (W_CNT1 - W_CNT0);
+    cmm::SideDesc& sd = side[q];
+    sd.X = X[q]; sd.ld = ld[q]; sd.scale = sc[q]; sd.n = (int)nn[q]; sd.hs = hsv[q];
+    sd.Lcap = spec.Lcap[q];
+    sd.Lrow = g.W * sd.Lcap;
+    sd.cnt = (int32_t*)ptr.p[W_CNT0 + o];
+    sd.pos = (int32_t*)ptr.p[W_POS0 + o];
+    sd.ent = (uint32_t*)ptr.p[W_ENT0 + o];
+    sd.tab = (uint32_t*)ptr.p[W_TAB0 + o];
+    sd.cntp = (int32_t*)ptr.p[W_CNTP0 + o];
+    sd.moff = (int32_t*)ptr.p[W_MOFF0 + o];
+    sd.fill = (int32_t*)ptr.p[W_FILL0 + o];
+    sd.perm = (int32_t*)ptr.p[W_PERM0 + o];
+    sd.segcount = (int32_t*)ptr.p[W_SEG0 + o];
+    sd.lseg = (int32_t*)ptr.p[W_LSEG0 + o];
+    sd.SA = (float*)ptr.p[W_SA0 + o];
+    sd.colmax = (float*)ptr.p[W_CMAX0 + o];
+  }
+}
+
+// Hash tables (when `pdev` holds parameters), bucket counts and the bucket
+// layout of both sides; `oflow` is set when a layout segment overflows.
+int enqueue_layout(cmm_ctx* c, const cmm::Geometry& g, cmm::SideDesc side[2],
+                   const uint64_t* pdev, int32_t* oflow, hipStream_t s) {
   CMM_HIP(c, cmm::launch_fill_i32(oflow, 1, 0, s));
   {
     Scope sc_(c, "hash");
-    if (sk->has_params) {
-      CMM_HIP(c, hipMemcpyAsync(pdev, sk->params.data(), sizeof(uint64_t) * g.d * 8,
-                                hipMemcpyHostToDevice, s));
+    if (pdev)
       for (int q = 0; q < 2; ++q) CMM_HIP(c, cmm::launch_hash(pdev, q, g, side[q], s));
-    }
     for (int q = 0; q < 2; ++q) CMM_HIP(c, cmm::launch_count(g, side[q], s));
   }
   {
     Scope sc_(c, "layout");
     for (int q = 0; q < 2; ++q) CMM_HIP(c, cmm::launch_layout(g, side[q], oflow, s));
   }
+  return CMM_OK;
+}
+
+// Every kernel of one sketch product, in stream order, on stream `s`: no
+// allocation, no host synchronisation, no host-to-device copy (hash
+// parameters are already at `pdev`), so the sequence can be captured.
+int enqueue_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Geometry& g,
+                    const WsSpec& spec, const WsPtrs& ptr, const uint64_t* pdev, hipStream_t s) {
+  cmm::SideDesc side[2];
+  bind_sides(g, sk, op, spec, ptr, side);
+  double2* tw64; float2* tw32;
+  int rc = get_twiddles(c, g.b, &tw64, &tw32);
+  if (rc) return rc;
+  rc = enqueue_layout(c, g, side, pdev, (int32_t*)ptr.p[W_OFLOW], s);
+  if (rc) return rc;
   {
     Scope sc_(c, "countsketch");
-    for (int q = 0; q < 2; ++q) CMM_HIP(c, cmm::launch_countsketch(dtype, g, side[q], s));
+    for (int q = 0; q < 2; ++q) CMM_HIP(c, cmm::launch_countsketch(op.dtype, g, side[q], s));
   }
   {
     Scope sc_(c, "fft_mac");
-    CMM_HIP(c, cmm::launch_fft_mac(g, side[0], side[1], tw32, Ppart, s));
+    CMM_HIP(c, cmm::launch_fft_mac(g, side[0], side[1], tw32, (float2*)ptr.p[W_PPART], s));
   }
   {
     Scope sc_(c, "ifft");
-    CMM_HIP(c, cmm::launch_ifft(g, Ppart, work0, work1, tw64, sk->c64, s));
-    if (flags & CMM_SUBTRACT_DIAG) {
+    CMM_HIP(c, cmm::launch_ifft(g, (float2*)ptr.p[W_PPART], (double2*)ptr.p[W_WORK0],
+                                (double2*)ptr.p[W_WORK1], tw64, sk->c64, s));
+    if (op.flags & CMM_SUBTRACT_DIAG) {
       const int n = (int)sk->n1;
-      const int kch = (int)std::max<int64_t>(1, std::min<int64_t>(sk->m, 1 + 4096 / ((n + 255) / 256)));
-      double* partial = w.get<double>((size_t)kch * n);
-      double* diag = w.get<double>((size_t)n);
-      if (!partial || !diag) return fail(c, CMM_ENOMEM, "workspace allocation failed");
-      CMM_HIP(c, cmm::launch_diag(dtype, side[0], side[1], g.m, n, partial, kch, diag, s));
-      CMM_HIP(c, cmm::launch_sub_diag(g, sk->hs1, sk->hs2, (int)sk->n1, (int)sk->n3, diag, n,
-                                      sk->c64, s));
+      CMM_HIP(c, cmm::launch_diag(op.dtype, side[0], side[1], g.m, n, (double*)ptr.p[W_PARTIAL],
+                                  spec.kch, (double*)ptr.p[W_DIAG], s));
+      CMM_HIP(c, cmm::launch_sub_diag(g, sk->hs1, sk->hs2, (int)sk->n1, (int)sk->n3,
+                                      (double*)ptr.p[W_DIAG], n, sk->c64, s));
     }
     CMM_HIP(c, cmm::launch_to_f32(sk->c64, sk->c32, (int64_t)g.d * g.b, s));
   }
-  *overflowed = false;
-  if (!async) {
-    CMM_HIP(c, hipMemcpyAsync(c->pinned_u32, oflow, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    CMM_HIP(c, hipStreamSynchronize(s));
-    *overflowed = c->pinned_u32[0] != 0;
-  }
   return CMM_OK;
+}
+
+// One product on the context stream with a workspace from the cache.
+int run_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Tuning& tu,
+                bool safe_layout, bool* overflowed) {
+  hipStream_t s = c->stream;
+  const bool async = op.flags & CMM_ASYNC;
+  const cmm::Geometry g = make_geometry(sk->b, sk->d, sk->m, tu);
+  const WsSpec spec = ws_spec(g, sk->n1, sk->n3, safe_layout || async, op.flags);
+  WsPtrs ptr;
+  std::vector<void*> owned;
+  uint64_t* pdev = nullptr;
+  int rc = ws_alloc(c, spec, ptr, owned);
+  if (rc == CMM_OK && sk->has_params) {
+    pdev = (uint64_t*)dalloc(c, sizeof(uint64_t) * sk->d * 8);
+    if (!pdev) rc = fail(c, CMM_ENOMEM, "workspace allocation failed");
+    else owned.push_back(pdev);
+  }
+  if (rc == CMM_OK && pdev) {
+    hipError_t e = hipMemcpyAsync(pdev, sk->params.data(), sizeof(uint64_t) * sk->d * 8,
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) rc = fail(c, CMM_EHIP, "parameter upload failed");
+  }
+  if (rc == CMM_OK) rc = enqueue_product(c, sk, op, g, spec, ptr, pdev, s);
+  *overflowed = false;
+  if (rc == CMM_OK && !async) {
+    hipError_t e1 = hipMemcpyAsync(c->pinned_u32, ptr.p[W_OFLOW], sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    if (e1 != hipSuccess || e2 != hipSuccess) rc = fail(c, CMM_EHIP, "stream synchronisation failed");
+    else *overflowed = c->pinned_u32[0] != 0;
+  }
+  ws_release(c, owned);   // stream-ordered reuse: later work on this stream follows
+  return rc;
+}
+
+// Device buffers of a sketch whose sizes are set (frees what it got on failure).
+bool alloc_sketch(cmm_sketch* sk) {
+  cmm_ctx* c = sk->ctx;
+  sk->hs1 = (int32_t*)dalloc(c, sizeof(int32_t) * sk->d * sk->n1);
+  sk->hs2 = (int32_t*)dalloc(c, sizeof(int32_t) * sk->d * sk->n3);
+  sk->c64 = (double*)dalloc(c, sizeof(double) * sk->d * sk->b);
+  sk->c32 = (float*)dalloc(c, sizeof(float) * sk->d * sk->b);
+  if (sk->hs1 && sk->hs2 && sk->c64 && sk->c32) return true;
+  dfree(c, sk->hs1); dfree(c, sk->hs2); dfree(c, sk->c64); dfree(c, sk->c32);
+  sk->hs1 = sk->hs2 = nullptr; sk->c64 = nullptr; sk->c32 = nullptr;
+  return false;
+}
+
+void release_sketch(cmm_sketch* sk) {
+  cmm_ctx* c = sk->ctx;
+  dfree(c, sk->hs1); dfree(c, sk->hs2); dfree(c, sk->c64); dfree(c, sk->c32);
+  sk->magic = kDeadMagic;
+  delete sk;
 }
 
 int product_common(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
@@ -365,12 +511,7 @@ int product_common(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int6
       params_from_seed(seed, d, sk->params);
     }
   }
-  sk->hs1 = (int32_t*)dalloc(ctx, sizeof(int32_t) * d * n1);
-  sk->hs2 = (int32_t*)dalloc(ctx, sizeof(int32_t) * d * n3);
-  sk->c64 = (double*)dalloc(ctx, sizeof(double) * d * b);
-  sk->c32 = (float*)dalloc(ctx, sizeof(float) * d * b);
-  if (!sk->hs1 || !sk->hs2 || !sk->c64 || !sk->c32) {
-    dfree(ctx, sk->hs1); dfree(ctx, sk->hs2); dfree(ctx, sk->c64); dfree(ctx, sk->c32);
+  if (!alloc_sketch(sk)) {
     delete sk;
     return fail(ctx, CMM_ENOMEM, "sketch allocation failed");
   }
@@ -381,11 +522,334 @@ int product_common(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int6
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) { cmm_sketch_free(sk); return fail(ctx, CMM_EHIP, "table upload failed"); }
   }
   bool over = false;
-  rc = run_product(ctx, sk, A, lda, B, ldb, dtype, scaleA, scaleB, flags, false, &over);
-  if (rc == CMM_OK && over)
-    rc = run_product(ctx, sk, A, lda, B, ldb, dtype, scaleA, scaleB, flags, true, &over);
+  const Operands op{A, lda, B, ldb, dtype, scaleA, scaleB, flags};
+  const cmm::Tuning tu = lookup_tuning(ctx, n1, m, n3, b, d, dtype);
+  rc = run_product(ctx, sk, op, tu, false, &over);
+  if (rc == CMM_OK && over) rc = run_product(ctx, sk, op, tu, true, &over);
   if (rc != CMM_OK) { cmm_sketch_free(sk); return rc; }
   *out = sk;
+  return CMM_OK;
+}
+
+TuneKey tune_key(int64_t n1, int64_t m, int64_t n3, int64_t b, int d, int dtype) {
+  return TuneKey{ilog2(b), ilog2(n1), ilog2(m), ilog2(n3), d, dtype};
+}
+
+cmm::Tuning lookup_tuning(const cmm_ctx* c, int64_t n1, int64_t m, int64_t n3, int64_t b, int d,
+                          int dtype) {
+  auto it = c->tuning.find(tune_key(n1, m, n3, b, d, dtype));
+  return it != c->tuning.end() ? it->second.tu : default_tuning(b);
+}
+
+bool valid_tuning(const cmm::Tuning& t) {
+  return t.log2c >= 4 && t.log2c <= cmm::kMaxLog2C && t.kmax >= 1 && t.kmax <= cmm::kMaxKPerBlock &&
+         t.cs_blocks >= 1 && t.cs_blocks <= (1 << 20);
+}
+
+int check_dims(cmm_ctx* c, int64_t n1, int64_t m, int64_t n3, int64_t b, int32_t d, int32_t dtype) {
+  static const char dummy = 0;
+  return check_operands(c, &dummy, n1, &dummy, n3, n1, m, n3, dtype, b, d);
+}
+
+// Mean time of one product under tuning `tu` on the synthetic operands of
+// `sk` (3 back-to-back runs after a warm-up run on the context stream).
+int time_candidate(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Tuning& tu,
+                   const uint64_t* pdev, hipEvent_t ev0, hipEvent_t ev1, double* ms) {
+  hipStream_t s = c->stream;
+  const cmm::Geometry g = make_geometry(sk->b, sk->d, sk->m, tu);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const WsSpec spec = ws_spec(g, sk->n1, sk->n3, attempt == 1, op.flags);
+    WsPtrs ptr;
+    std::vector<void*> owned;
+    int rc = ws_alloc(c, spec, ptr, owned);
+    if (rc == CMM_OK) rc = enqueue_product(c, sk, op, g, spec, ptr, pdev, s);
+    if (rc == CMM_OK && hipMemcpyAsync(c->pinned_u32, ptr.p[W_OFLOW], sizeof(int32_t),
+                                       hipMemcpyDeviceToHost, s) != hipSuccess)
+      rc = fail(c, CMM_EHIP, "overflow flag copy failed");
+    if (rc == CMM_OK && hipStreamSynchronize(s) != hipSuccess)
+      rc = fail(c, CMM_EHIP, "stream synchronisation failed");
+    if (rc == CMM_OK && c->pinned_u32[0] != 0 && attempt == 0) { ws_release(c, owned); continue; }
+    if (rc == CMM_OK && hipEventRecord(ev0, s) != hipSuccess) rc = fail(c, CMM_EHIP, "event record failed");
+    for (int r = 0; r < 3 && rc == CMM_OK; ++r) rc = enqueue_product(c, sk, op, g, spec, ptr, pdev, s);
+    if (rc == CMM_OK && hipEventRecord(ev1, s) != hipSuccess) rc = fail(c, CMM_EHIP, "event record failed");
+    if (rc == CMM_OK && hipEventSynchronize(ev1) != hipSuccess) rc = fail(c, CMM_EHIP, "event wait failed");
+    float t = 0.f;
+    if (rc == CMM_OK && hipEventElapsedTime(&t, ev0, ev1) != hipSuccess) rc = fail(c, CMM_EHIP, "event time failed");
+    if (rc == CMM_OK) *ms = t / 3.0;
+    (void)hipStreamSynchronize(s);
+    ws_release(c, owned);
+    return rc;
+  }
+  return fail(c, CMM_EHIP, "layout overflow with the safe layout");
+}
+
+// Coordinate search over the geometry of one size class: the FFT row
+// length first, then the number of k per spectral block, then the number
+// of count-sketch blocks; candidates that give the same launch shapes as
+// one already timed are skipped.
+int autotune_class(cmm_ctx* c, int64_t n1, int64_t m, int64_t n3, int64_t b, int d, int dtype,
+                   TuneEntry* best) {
+  hipStream_t s = c->stream;
+  const size_t esz = dtype == CMM_F32 ? 4 : (dtype == CMM_BF16 ? 2 : 1);
+  Work w(c);
+  void* A = w.get<uint8_t>(esz * n1 * m);
+  void* B = w.get<uint8_t>(esz * m * n3);
+  uint64_t* pdev = w.get<uint64_t>((size_t)d * 8);
+  if (!A || !B || !pdev) return fail(c, CMM_ENOMEM, "autotune operand allocation failed");
+  CMM_HIP(c, cmm::launch_fill_random(A, n1 * m, dtype, 0x243F6A8885A308D3ull, s));
+  CMM_HIP(c, cmm::launch_fill_random(B, m * n3, dtype, 0x13198A2E03707344ull, s));
+  cmm_sketch* sk = new cmm_sketch();
+  sk->ctx = c; sk->n1 = n1; sk->m = m; sk->n3 = n3; sk->b = b; sk->d = d; sk->log2b = ilog2(b);
+  sk->has_params = true;
+  params_from_seed(0xA4093822299F31D0ull, d, sk->params);
+  if (!alloc_sketch(sk)) { delete sk; return fail(c, CMM_ENOMEM, "autotune sketch allocation failed"); }
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int rc = CMM_OK;
+  if (hipMemcpyAsync(pdev, sk->params.data(), sizeof(uint64_t) * d * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+    rc = fail(c, CMM_EHIP, "autotune set-up failed");
+  const bool prof = c->prof;
+  c->prof = false;
+  const Operands op{A, n1, B, n3, dtype, nullptr, nullptr, 0};
+  cmm::Tuning cur = default_tuning(b);
+  double cur_ms = 0.0;
+  if (rc == CMM_OK) rc = time_candidate(c, sk, op, cur, pdev, ev0, ev1, &cur_ms);
+  auto shape = [&](const cmm::Tuning& t) {
+    const cmm::Geometry g = make_geometry(b, d, m, t);
+    const int kb = std::max<int>(1, (int)(m / g.cs_blocks));
+    return std::make_tuple(g.log2c, g.KS, (int)((m + kb - 1) / kb));
+  };
+  std::vector<std::tuple<int, int, int>> seen{shape(cur)};
+  for (int axis = 0; axis < 3 && rc == CMM_OK; ++axis) {
+    const std::vector<int> vals = axis == 0 ? std::vector<int>{10, 11, 12, 13}
+                                : axis == 1 ? std::vector<int>{32, 64, 128}
+                                            : std::vector<int>{512, 1024, 2048, 4096};
+    const cmm::Tuning base = cur;
+    for (int v : vals) {
+      cmm::Tuning t = base;
+      (axis == 0 ? t.log2c : axis == 1 ? t.kmax : t.cs_blocks) = v;
+      const auto sh = shape(t);
+      if (std::find(seen.begin(), seen.end(), sh) != seen.end()) continue;
+      seen.push_back(sh);
+      double ms = 0.0;
+      rc = time_candidate(c, sk, op, t, pdev, ev0, ev1, &ms);
+      if (rc != CMM_OK) break;
+      if (ms < cur_ms) { cur = t; cur_ms = ms; }
+    }
+  }
+  c->prof = prof;
+  (void)hipStreamSynchronize(s);
+  if (ev0) hipEventDestroy(ev0);
+  if (ev1) hipEventDestroy(ev1);
+  release_sketch(sk);
+  if (rc == CMM_OK) { best->tu = cur; best->ms = cur_ms; }
+  return rc;
+}
+
+const char* device_arch(cmm_ctx* c) {
+  if (c->arch.empty()) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+      std::string a = prop.gcnArchName;
+      c->arch = a.substr(0, a.find(':'));
+    } else {
+      c->arch = "unknown";
+    }
+  }
+  return c->arch.c_str();
+}
+
+int load_tuning(cmm_ctx* c, const char* path, bool missing_ok) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return missing_ok ? CMM_OK : fail(c, CMM_EINVAL, std::string("cannot open ") + path);
+  const std::string arch = device_arch(c);
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    char a[64] = {0};
+    TuneKey k;
+    TuneEntry e;
+    const int got = std::sscanf(line,
+        " {\"arch\": \"%63[^\"]\", \"log2b\": %d, \"ln1\": %d, \"lm\": %d, \"ln3\": %d, \"d\": %d, "
+        "\"dtype\": %d, \"log2c\": %d, \"kmax\": %d, \"cs_blocks\": %d, \"ms\": %lf}",
+        a, &k.log2b, &k.ln1, &k.lm, &k.ln3, &k.d, &k.dtype, &e.tu.log2c, &e.tu.kmax,
+        &e.tu.cs_blocks, &e.ms);
+    if (got != 11 || arch != a || !valid_tuning(e.tu)) continue;
+    c->tuning[k] = e;
+  }
+  std::fclose(f);
+  return CMM_OK;
+}
+
+}  // namespace
+
+// A set of products recorded into one HIP graph.
+struct cmm_batch {
+  static constexpr int kMaxBranches = 4;
+  uint32_t magic = kBatchMagic;
+  cmm_ctx* ctx = nullptr;
+  std::vector<cmm_sketch*> sk;
+  std::vector<void*> owned;   // workspaces and hash parameters (context cache blocks)
+  int nbranch = 0;
+  hipStream_t streams[kMaxBranches] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kMaxBranches] = {};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+bool valid_batch(const cmm_batch* b) { return b && b->magic == kBatchMagic && valid_ctx(b->ctx); }
+
+// Release everything of a batch; its sketches are deleted too unless
+// `keep_sketches`, which hands them over as ordinary sketches.
+void destroy_batch(cmm_batch* bt, bool keep_sketches) {
+  cmm_ctx* c = bt->ctx;
+  (void)hipStreamSynchronize(c->stream);
+  if (bt->exec) hipGraphExecDestroy(bt->exec);
+  if (bt->graph) hipGraphDestroy(bt->graph);
+  for (int q = 0; q < cmm_batch::kMaxBranches; ++q) {
+    if (bt->streams[q]) { (void)hipStreamSynchronize(bt->streams[q]); hipStreamDestroy(bt->streams[q]); }
+    if (bt->join[q]) hipEventDestroy(bt->join[q]);
+  }
+  if (bt->fork) hipEventDestroy(bt->fork);
+  for (void* p : bt->owned) dfree(c, p);
+  for (cmm_sketch* sk : bt->sk) {
+    if (keep_sketches) sk->owner = nullptr;
+    else release_sketch(sk);
+  }
+  bt->magic = kDeadMagic;
+  delete bt;
+}
+
+struct BatchItem {
+  cmm::Geometry g;
+  WsSpec spec;
+  Operands op;
+  const uint64_t* pdev = nullptr;
+  double cost = 0.0;
+  int branch = 0;
+};
+
+// Relative cost of a product for spreading a batch over graph branches:
+// spectral work (a C-point FFT per row, per k and side) plus the fold and
+// count-sketch work over the hashed entries.
+double product_cost(const cmm::Geometry& g, int64_t n1, int64_t n3) {
+  const double C = (double)(1 << g.log2c);
+  return (double)g.d * g.m * (2.0 * g.rows * C * g.log2c + 8.0 * (n1 + n3));
+}
+
+int build_batch(cmm_ctx* c, const cmm_problem* pr, int count, uint32_t flags, cmm_batch* bt) {
+  hipStream_t s = c->stream;
+  std::vector<BatchItem> it(count);
+  // sketches, hash parameters, geometry, twiddle tables
+  for (int i = 0; i < count; ++i) {
+    const cmm_problem& p = pr[i];
+    cmm_sketch* sk = new cmm_sketch();
+    sk->ctx = c; sk->n1 = p.n1; sk->m = p.m; sk->n3 = p.n3; sk->b = p.b; sk->d = p.d;
+    sk->log2b = ilog2(p.b);
+    sk->has_params = true;
+    params_from_seed(p.seed, p.d, sk->params);
+    if (!alloc_sketch(sk)) { delete sk; return fail(c, CMM_ENOMEM, "sketch allocation failed"); }
+    sk->owner = bt;
+    bt->sk.push_back(sk);
+    uint64_t* pdev = (uint64_t*)dalloc(c, sizeof(uint64_t) * p.d * 8);
+    if (!pdev) return fail(c, CMM_ENOMEM, "parameter buffer allocation failed");
+    bt->owned.push_back(pdev);
+    CMM_HIP(c, hipMemcpyAsync(pdev, sk->params.data(), sizeof(uint64_t) * p.d * 8,
+                              hipMemcpyHostToDevice, s));
+    if ((flags & CMM_AUTOTUNE) && !c->tuning.count(tune_key(p.n1, p.m, p.n3, p.b, p.d, p.dtype))) {
+      TuneEntry e;
+      int rc = autotune_class(c, p.n1, p.m, p.n3, p.b, p.d, p.dtype, &e);
+      if (rc) return rc;
+      c->tuning[tune_key(p.n1, p.m, p.n3, p.b, p.d, p.dtype)] = e;
+    }
+    it[i].g = make_geometry(p.b, p.d, p.m, lookup_tuning(c, p.n1, p.m, p.n3, p.b, p.d, p.dtype));
+    it[i].op = Operands{p.A, p.lda, p.B, p.ldb, p.dtype, p.scaleA, p.scaleB, p.flags};
+    it[i].pdev = pdev;
+    it[i].cost = product_cost(it[i].g, p.n1, p.n3);
+    double2* t64; float2* t32;
+    int rc = get_twiddles(c, p.b, &t64, &t32);
+    if (rc) return rc;
+  }
+  // bucket layouts: the hash functions fix them, so one layout pass per
+  // problem decides whether the compact segment capacity holds for good
+  for (int i = 0; i < count; ++i) {
+    BatchItem& x = it[i];
+    WsSpec probe = ws_spec(x.g, pr[i].n1, pr[i].n3, false, 0);
+    for (int k : {W_SA0, W_SA1, W_CMAX0, W_CMAX1, W_PPART, W_WORK0, W_WORK1}) probe.count[k] = 0;
+    WsPtrs ptr;
+    std::vector<void*> owned;
+    int rc = ws_alloc(c, probe, ptr, owned);
+    cmm::SideDesc side[2];
+    if (rc == CMM_OK) {
+      bind_sides(x.g, bt->sk[i], x.op, probe, ptr, side);
+      rc = enqueue_layout(c, x.g, side, x.pdev, (int32_t*)ptr.p[W_OFLOW], s);
+    }
+    if (rc == CMM_OK && (hipMemcpyAsync(c->pinned_u32, ptr.p[W_OFLOW], sizeof(int32_t),
+                                        hipMemcpyDeviceToHost, s) != hipSuccess ||
+                         hipStreamSynchronize(s) != hipSuccess))
+      rc = fail(c, CMM_EHIP, "layout pass failed");
+    ws_release(c, owned);
+    if (rc) return rc;
+    x.spec = ws_spec(x.g, pr[i].n1, pr[i].n3, c->pinned_u32[0] != 0, pr[i].flags);
+  }
+  // longest product first onto the least loaded branch
+  bt->nbranch = std::min(count, (int)cmm_batch::kMaxBranches);
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return it[a].cost > it[b2].cost; });
+  std::vector<double> load(bt->nbranch, 0.0);
+  for (int i : order) {
+    const int br = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    it[i].branch = br;
+    load[br] += it[i].cost;
+  }
+  // one workspace per branch, each buffer as large as its largest user
+  std::vector<WsPtrs> ws(bt->nbranch);
+  for (int br = 0; br < bt->nbranch; ++br) {
+    WsSpec mx;
+    for (int i = 0; i < count; ++i)
+      if (it[i].branch == br)
+        for (int k = 0; k < W_COUNT; ++k) mx.count[k] = std::max(mx.count[k], it[i].spec.count[k]);
+    int rc = ws_alloc(c, mx, ws[br], bt->owned);
+    if (rc) return rc;
+  }
+  for (int br = 0; br < bt->nbranch; ++br) {
+    CMM_HIP(c, hipStreamCreateWithFlags(&bt->streams[br], hipStreamNonBlocking));
+    CMM_HIP(c, hipEventCreateWithFlags(&bt->join[br], hipEventDisableTiming));
+  }
+  CMM_HIP(c, hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming));
+  CMM_HIP(c, hipStreamSynchronize(s));
+  // capture: branch 0 forks the others and joins them at the end
+  hipStream_t s0 = bt->streams[0];
+  const bool prof = c->prof;
+  c->prof = false;
+  int rc = CMM_OK;
+  if (hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    c->prof = prof;
+    return fail(c, CMM_EHIP, "hipStreamBeginCapture failed");
+  }
+  if (hipEventRecord(bt->fork, s0) != hipSuccess) rc = fail(c, CMM_EHIP, "fork record failed");
+  for (int br = 1; br < bt->nbranch && rc == CMM_OK; ++br)
+    if (hipStreamWaitEvent(bt->streams[br], bt->fork, 0) != hipSuccess)
+      rc = fail(c, CMM_EHIP, "fork wait failed");
+  for (int i : order) {
+    if (rc) break;
+    rc = enqueue_product(c, bt->sk[i], it[i].op, it[i].g, it[i].spec, ws[it[i].branch],
+                         it[i].pdev, bt->streams[it[i].branch]);
+  }
+  for (int br = 1; br < bt->nbranch; ++br) {
+    (void)hipEventRecord(bt->join[br], bt->streams[br]);
+    (void)hipStreamWaitEvent(s0, bt->join[br], 0);
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(s0, &graph);
+  c->prof = prof;
+  bt->graph = graph;
+  if (rc) return rc;
+  if (ec != hipSuccess || !graph) return fail(c, CMM_EHIP, std::string("graph capture failed: ") + hipGetErrorString(ec));
+  CMM_HIP(c, hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
   return CMM_OK;
 }
 
@@ -433,6 +897,12 @@ int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out) {
     delete c;
     return CMM_ENOMEM;
   }
+  if (cmm::prepare_countsketch() != hipSuccess || cmm::prepare_fft_mac() != hipSuccess) {
+    hipHostFree(c->pinned_u32);
+    delete c;
+    return CMM_EHIP;
+  }
+  if (const char* path = std::getenv("CMM_TUNE_CACHE")) load_tuning(c, path, true);
   *out = c;
   return CMM_OK;
 }
@@ -500,10 +970,8 @@ int cmm_sketch_product_tables(cmm_ctx* ctx, const void* A, int64_t lda, const vo
 
 int cmm_sketch_free(cmm_sketch* sk) {
   if (!valid_sketch(sk)) return CMM_EINVAL;
-  cmm_ctx* c = sk->ctx;
-  dfree(c, sk->hs1); dfree(c, sk->hs2); dfree(c, sk->c64); dfree(c, sk->c32);
-  sk->magic = kDeadMagic;
-  delete sk;
+  if (sk->owner) return fail(sk->ctx, CMM_ESTATE, "the sketch belongs to a batch");
+  release_sketch(sk);
   return CMM_OK;
 }
 
@@ -562,7 +1030,7 @@ int cmm_sketch_subtract_diagonal(cmm_sketch* sk, const double* diag, int64_t len
   cmm_ctx* c = sk->ctx;
   if (!diag || len < 0 || len > std::min(sk->n1, sk->n3)) return fail(c, CMM_EINVAL, "bad diag");
   if (len == 0) return CMM_OK;
-  cmm::Geometry g = make_geometry(sk->b, sk->d, sk->m);
+  cmm::Geometry g = make_geometry(sk->b, sk->d, sk->m, cmm::Tuning());
   CMM_HIP(c, cmm::launch_sub_diag(g, sk->hs1, sk->hs2, (int)sk->n1, (int)sk->n3, diag, (int)len, sk->c64, c->stream));
   CMM_HIP(c, cmm::launch_to_f32(sk->c64, sk->c32, sk->d * sk->b, c->stream));
   CMM_HIP(c, hipStreamSynchronize(c->stream));
@@ -699,6 +1167,151 @@ int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int6
   CMM_HIP(c, hipMemcpyAsync(out_val, ov, sizeof(float) * K, hipMemcpyDeviceToHost, s));
   CMM_HIP(c, hipStreamSynchronize(s));
   return CMM_OK;
+}
+
+int cmm_batch_create(cmm_ctx* ctx, const cmm_problem* probs, int32_t count, uint32_t flags,
+                     cmm_batch** out) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  if (!out) return fail(ctx, CMM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!probs) return fail(ctx, CMM_EINVAL, "probs is NULL");
+  if (count < 1 || count > 4096) return fail(ctx, CMM_EINVAL, "count must be in [1, 4096]");
+  if (flags & ~CMM_AUTOTUNE) return fail(ctx, CMM_EINVAL, "unknown flag");
+  for (int i = 0; i < count; ++i) {
+    const cmm_problem& p = probs[i];
+    int rc = check_operands(ctx, p.A, p.lda, p.B, p.ldb, p.n1, p.m, p.n3, p.dtype, p.b, p.d);
+    if (rc) return fail(ctx, rc, "problem " + std::to_string(i) + ": " + ctx->last_error);
+    if (p.flags & ~CMM_SUBTRACT_DIAG)
+      return fail(ctx, CMM_EINVAL, "problem " + std::to_string(i) + ": unknown flag");
+    if (p.reserved != 0) return fail(ctx, CMM_EINVAL, "problem " + std::to_string(i) + ": reserved field set");
+    if ((p.flags & CMM_SUBTRACT_DIAG) && p.n1 != p.n3)
+      return fail(ctx, CMM_EINVAL, "problem " + std::to_string(i) + ": CMM_SUBTRACT_DIAG needs n1 == n3");
+    if (p.dtype != CMM_FP8_E4M3 && (p.scaleA || p.scaleB))
+      return fail(ctx, CMM_EINVAL, "problem " + std::to_string(i) + ": scales are only taken with CMM_FP8_E4M3");
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, CMM_EHIP, "hipSetDevice failed");
+  cmm_batch* bt = new cmm_batch();
+  bt->ctx = ctx;
+  int rc = build_batch(ctx, probs, count, flags, bt);
+  if (rc) {
+    const std::string msg = ctx->last_error;
+    destroy_batch(bt, false);
+    ctx->last_error = msg;
+    return rc;
+  }
+  *out = bt;
+  return CMM_OK;
+}
+
+int cmm_batch_run(cmm_batch* batch, uint32_t flags) {
+  if (!valid_batch(batch)) return CMM_EINVAL;
+  cmm_ctx* c = batch->ctx;
+  if (flags & ~CMM_ASYNC) return fail(c, CMM_EINVAL, "unknown flag");
+  CMM_HIP(c, hipSetDevice(c->device));
+  {
+    Scope sc_(c, "batch");
+    CMM_HIP(c, hipGraphLaunch(batch->exec, c->stream));
+  }
+  if (!(flags & CMM_ASYNC)) CMM_HIP(c, hipStreamSynchronize(c->stream));
+  return CMM_OK;
+}
+
+int cmm_batch_sketch(cmm_batch* batch, int32_t index, cmm_sketch** out) {
+  if (!valid_batch(batch)) return CMM_EINVAL;
+  if (!out) return fail(batch->ctx, CMM_EINVAL, "out is NULL");
+  if (index < 0 || index >= (int32_t)batch->sk.size()) return fail(batch->ctx, CMM_EINVAL, "index out of range");
+  *out = batch->sk[index];
+  return CMM_OK;
+}
+
+int cmm_batch_free(cmm_batch* batch) {
+  if (!valid_batch(batch)) return CMM_EINVAL;
+  destroy_batch(batch, false);
+  return CMM_OK;
+}
+
+int cmm_sketch_product_batched(cmm_ctx* ctx, const cmm_problem* probs, int32_t count,
+                               cmm_sketch** outs) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  if (!outs) return fail(ctx, CMM_EINVAL, "outs is NULL");
+  cmm_batch* bt = nullptr;
+  int rc = cmm_batch_create(ctx, probs, count, 0, &bt);
+  if (rc) return rc;
+  rc = cmm_batch_run(bt, 0);
+  if (rc) { const std::string msg = ctx->last_error; destroy_batch(bt, false); ctx->last_error = msg; return rc; }
+  for (int i = 0; i < count; ++i) outs[i] = bt->sk[i];
+  destroy_batch(bt, true);
+  return CMM_OK;
+}
+
+int cmm_autotune(cmm_ctx* ctx, int64_t n1, int64_t m, int64_t n3, int64_t b, int32_t d,
+                 int32_t dtype, int32_t* tuning, double* best_ms) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  int rc = check_dims(ctx, n1, m, n3, b, d, dtype);
+  if (rc) return rc;
+  CMM_HIP(ctx, hipSetDevice(ctx->device));
+  TuneEntry e;
+  rc = autotune_class(ctx, n1, m, n3, b, d, dtype, &e);
+  if (rc) return rc;
+  ctx->tuning[tune_key(n1, m, n3, b, d, dtype)] = e;
+  if (tuning) { tuning[0] = e.tu.log2c; tuning[1] = e.tu.kmax; tuning[2] = e.tu.cs_blocks; }
+  if (best_ms) *best_ms = e.ms;
+  return CMM_OK;
+}
+
+int cmm_tuning_get(const cmm_ctx* ctx, int64_t n1, int64_t m, int64_t n3, int64_t b, int32_t d,
+                   int32_t dtype, int32_t* tuning) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  cmm_ctx* c = const_cast<cmm_ctx*>(ctx);
+  if (!tuning) return fail(c, CMM_EINVAL, "tuning is NULL");
+  int rc = check_dims(c, n1, m, n3, b, d, dtype);
+  if (rc) return rc;
+  const cmm::Geometry g = make_geometry(b, d, m, lookup_tuning(ctx, n1, m, n3, b, d, dtype));
+  const cmm::Tuning t = lookup_tuning(ctx, n1, m, n3, b, d, dtype);
+  tuning[0] = g.log2c; tuning[1] = t.kmax; tuning[2] = g.cs_blocks;
+  return CMM_OK;
+}
+
+int cmm_tuning_set(cmm_ctx* ctx, int64_t n1, int64_t m, int64_t n3, int64_t b, int32_t d,
+                   int32_t dtype, const int32_t* tuning) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  if (!tuning) return fail(ctx, CMM_EINVAL, "tuning is NULL");
+  int rc = check_dims(ctx, n1, m, n3, b, d, dtype);
+  if (rc) return rc;
+  TuneEntry e;
+  e.tu.log2c = tuning[0]; e.tu.kmax = tuning[1]; e.tu.cs_blocks = tuning[2];
+  if (!valid_tuning(e.tu)) return fail(ctx, CMM_EINVAL, "tuning out of range");
+  ctx->tuning[tune_key(n1, m, n3, b, d, dtype)] = e;
+  return CMM_OK;
+}
+
+int cmm_tuning_save(const cmm_ctx* ctx, const char* path) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  cmm_ctx* c = const_cast<cmm_ctx*>(ctx);
+  if (!path) return fail(c, CMM_EINVAL, "path is NULL");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(c, CMM_EINVAL, std::string("cannot write ") + path);
+  const std::string arch = device_arch(c);
+  std::fprintf(f, "[\n");
+  size_t q = 0;
+  for (const auto& kv : c->tuning) {
+    const TuneKey& k = kv.first;
+    const TuneEntry& e = kv.second;
+    std::fprintf(f,
+                 " {\"arch\": \"%s\", \"log2b\": %d, \"ln1\": %d, \"lm\": %d, \"ln3\": %d, \"d\": %d, "
+                 "\"dtype\": %d, \"log2c\": %d, \"kmax\": %d, \"cs_blocks\": %d, \"ms\": %.6f}%s\n",
+                 arch.c_str(), k.log2b, k.ln1, k.lm, k.ln3, k.d, k.dtype, e.tu.log2c, e.tu.kmax,
+                 e.tu.cs_blocks, e.ms, ++q < c->tuning.size() ? "," : "");
+  }
+  std::fprintf(f, "]\n");
+  const bool ok = std::fclose(f) == 0;
+  return ok ? CMM_OK : fail(c, CMM_EINVAL, std::string("cannot write ") + path);
+}
+
+int cmm_tuning_load(cmm_ctx* ctx, const char* path) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  if (!path) return fail(ctx, CMM_EINVAL, "path is NULL");
+  return load_tuning(ctx, path, false);
 }
 
 }  // extern "C"

@@ -70,6 +70,16 @@ struct SideDesc {
   int Lrow;             // W * Lcap
 };
 
+// Launch-shape choices of one product (picked by the autotuner or defaults):
+// FFT row length 2^log2c (its radix sequence: 2^(log2c mod 4) then 16s),
+// at most kmax values of k per FFT block (the float32 partial-sum length),
+// and the number of countsketch blocks.
+struct Tuning {
+  int log2c = 12;
+  int kmax = 128;
+  int cs_blocks = 2048;
+};
+
 struct Geometry {
   int64_t b;
   int log2b;
@@ -82,6 +92,7 @@ struct Geometry {
   int R;                // rows of the four-step split = b / C
   int rows;             // computed rows (R/2 + 1, or 1 when R == 1)
   int KS;               // k-splits of the FFT kernel
+  int cs_blocks;        // countsketch blocks
 };
 
 // ---- kernel launchers (stream-ordered, return hipError_t) ----
@@ -91,6 +102,8 @@ hipError_t launch_hash(const uint64_t* params_dev, int side, const Geometry& g, 
                        hipStream_t s);
 hipError_t launch_count(const Geometry& g, SideDesc& sd, hipStream_t s);
 hipError_t launch_layout(const Geometry& g, SideDesc& sd, int32_t* overflow, hipStream_t s);
+hipError_t prepare_countsketch();
+hipError_t prepare_fft_mac();
 hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStream_t s);
 hipError_t launch_fft_mac(const Geometry& g, const SideDesc& a, const SideDesc& bside,
                           const float2* tw32, float2* Ppart, hipStream_t s);
@@ -102,6 +115,7 @@ hipError_t launch_sub_diag(const Geometry& g, const int32_t* hs1, const int32_t*
                            int n3, const double* diag, int len, double* c64, hipStream_t s);
 hipError_t launch_to_f32(const double* c64, float* c32, int64_t count, hipStream_t s);
 hipError_t launch_add_f64(double* dst, const double* src, int64_t count, hipStream_t s);
+hipError_t launch_fill_random(void* X, int64_t count, int dtype, uint64_t seed, hipStream_t s);
 
 struct DecodeDesc {
   const int32_t* hs1;   // [d][n1]

@@ -13,6 +13,8 @@
 // bound by HBM bandwidth.
 #include "cmm_internal.h"
 
+#include <algorithm>
+
 namespace cmm {
 
 __device__ __forceinline__ float e4m3fn_to_f32(uint32_t v) {
@@ -142,26 +144,35 @@ hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStr
   const bool vec = (sd.n % 4 == 0) && (sd.ld % 4 == 0) &&
                    ((uintptr_t)sd.X % (4 * esz) == 0) &&
                    (sd.scale == nullptr || (uintptr_t)sd.scale % 16 == 0);
-  // aim for ~1024 blocks
-  int kblock = (int)((int64_t)g.m / 1024);
+  int kblock = (int)((int64_t)g.m / std::max(1, g.cs_blocks));
   if (kblock < 1) kblock = 1;
   const int blocks = (g.m + kblock - 1) / kblock;
   const size_t lds = (size_t)sd.n * sizeof(float);
 #define CMM_CS(DTV, VV)                                                                     \
-  do {                                                                                      \
-    if (lds > 64 * 1024) {                                                                  \
-      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_countsketch<DTV, VV>), \
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-      if (e_ != hipSuccess) return e_;                                                      \
-    }                                                                                       \
-    hipLaunchKernelGGL((k_countsketch<DTV, VV>), dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, \
-                       g.W, kblock);                                                        \
-  } while (0)
+  hipLaunchKernelGGL((k_countsketch<DTV, VV>), dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, \
+                     g.W, kblock)
   if (dtype == 0) { if (vec) CMM_CS(0, true); else CMM_CS(0, false); }
   else if (dtype == 1) { if (vec) CMM_CS(1, true); else CMM_CS(1, false); }
   else { if (vec) CMM_CS(2, true); else CMM_CS(2, false); }
 #undef CMM_CS
   return hipGetLastError();
+}
+
+// Raise the dynamic LDS limit of every instantiation to the 96 KB a staged
+// row of up to 24576 floats needs (done once per context, outside any graph
+// capture).
+hipError_t prepare_countsketch() {
+  const void* fns[] = {reinterpret_cast<const void*>(&k_countsketch<0, true>),
+                       reinterpret_cast<const void*>(&k_countsketch<0, false>),
+                       reinterpret_cast<const void*>(&k_countsketch<1, true>),
+                       reinterpret_cast<const void*>(&k_countsketch<1, false>),
+                       reinterpret_cast<const void*>(&k_countsketch<2, true>),
+                       reinterpret_cast<const void*>(&k_countsketch<2, false>)};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace cmm

@@ -321,11 +321,6 @@ template <int L>
 static hipError_t launch_L(const FftArgs& a, hipStream_t s) {
   typedef FftShape<L> F;
   const size_t lds = (size_t)(2 * F::C + F::NMID + 16 * a.R) * sizeof(float2);
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_mac<L>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
   hipLaunchKernelGGL(k_fft_mac<L>, dim3(a.nwg), dim3(F::T), lds, s, a);
   return hipGetLastError();
 }
@@ -355,6 +350,21 @@ hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc&
     case 13: return launch_L<13>(a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Raise the dynamic LDS limit of every row length to 160 KB (done once per
+// context, outside any graph capture).
+hipError_t prepare_fft_mac() {
+  const void* fns[] = {reinterpret_cast<const void*>(&k_fft_mac<4>), reinterpret_cast<const void*>(&k_fft_mac<5>),
+                       reinterpret_cast<const void*>(&k_fft_mac<6>), reinterpret_cast<const void*>(&k_fft_mac<7>),
+                       reinterpret_cast<const void*>(&k_fft_mac<8>), reinterpret_cast<const void*>(&k_fft_mac<9>),
+                       reinterpret_cast<const void*>(&k_fft_mac<10>), reinterpret_cast<const void*>(&k_fft_mac<11>),
+                       reinterpret_cast<const void*>(&k_fft_mac<12>), reinterpret_cast<const void*>(&k_fft_mac<13>)};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace cmm

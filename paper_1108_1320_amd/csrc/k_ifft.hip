@@ -236,3 +236,29 @@ hipError_t launch_add_f64(double* dst, const double* src, int64_t count, hipStre
 }
 
 }  // namespace cmm
+
+namespace cmm {
+
+// Deterministic pseudo-random operand values for the autotuner's trial
+// products (SplitMix64 of the element index): uniform in [-1, 1) for f32,
+// its bf16 rounding, or fp8 codes of magnitude < 448.
+__global__ void k_fill_random(void* X, int64_t count, int dtype, uint64_t seed) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const float u = (float)(z >> 40) * 0x1p-23f - 1.0f;
+    if (dtype == 0) ((float*)X)[i] = u;
+    else if (dtype == 1) ((uint16_t*)X)[i] = (uint16_t)(__float_as_uint(u) >> 16);
+    else ((uint8_t*)X)[i] = (uint8_t)((z & 0x7E) | ((z >> 8) & 0x80));
+  }
+}
+
+hipError_t launch_fill_random(void* X, int64_t count, int dtype, uint64_t seed, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_random, dim3(grid_for(count)), dim3(256), 0, s, X, count, dtype, seed);
+  return hipGetLastError();
+}
+
+}  // namespace cmm

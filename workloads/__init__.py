@@ -37,7 +37,7 @@ import numpy as np
 __all__ = [
     "rng", "covariance_observations", "dct2_orthonormal", "transform_operands",
     "bf16_encode", "e4m3fn_encode", "e4m3fn_grid", "Workload", "make_workload",
-    "CONFIGS", "batched_sizes", "next_pow2",
+    "CONFIGS", "batched_sizes", "batched_workloads", "next_pow2",
 ]
 
 
@@ -276,4 +276,17 @@ def batched_sizes(count: int = 64, seed: int = 1005, lo: int = 512, hi: int = 81
         n = int(round(math.exp(g.uniform(math.log(lo), math.log(hi)))))
         pairs = int(g.integers(4, 129))
         out.append((n, next_pow2(8 * n), min(pairs, n // 2), 100000 + p, 2000 + 100 * 5 + p))
+    return out
+
+
+def batched_workloads(count: int = 64, seed: int = 1005, lo: int = 512, hi: int = 8192, d: int = 5,
+                      dtype: str = "bf16"):
+    """The batched covariance workload: one covariance product per entry of
+    ``batched_sizes`` (n = m, b = next power of two of 8n, 4..128 planted
+    pairs with rho in [0.5, 0.95], d repetitions, operands stored in
+    ``dtype``), each selecting its top-(planted pairs) over i < j."""
+    out = []
+    for p, (n, b, pairs, data_seed, hash_seed) in enumerate(batched_sizes(count, seed, lo, hi)):
+        out.append(covariance_workload(f"cfg5.{p}", n, n, pairs, (0.5, 0.95), b, d, pairs, dtype,
+                                       data_seed, hash_seed))
     return out
