@@ -15,6 +15,12 @@ Prints one JSON line.  ``value`` is the input GB/s of the whole step:
 bytes(A) + bytes(B) as stored, divided by the step time.  The same workload
 is also run with bf16 operands (``bf16_same_workload``) and both are checked
 against the float64 oracle.
+
+The batched form (``batched_form``; ``--workload 5`` makes it the headline):
+64 covariance products, n = m log-uniform in [512, 8192], b = next power of
+two of 8n, d = 5, bf16 operands, diagonal subtracted, recorded once into one
+HIP graph after autotuning every size class; one step is one graph replay
+plus the top-(planted pairs) selection of every product.
 """
 from __future__ import annotations
 
@@ -50,10 +56,11 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4])
+    p.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5])
     p.add_argument("--dtype", default=None, help="override the workload's dtype (f32/bf16/fp8)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-compare", action="store_true", help="skip the bf16 run of the same workload")
+    p.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -112,6 +119,84 @@ def run_timed(ctx, w, steps, warmup):
             "input_bytes": (w.n1 * w.m + w.m * w.n3) * esz}
 
 
+def run_batched(ctx, steps, warmup, with_oracle=True):
+    """The batched covariance workload as one graph replay per step."""
+    import numpy as np
+    import torch
+    import paper_1108_1320_amd as cmm
+    import workloads as W
+    t0 = time.perf_counter()
+    ws = W.batched_workloads()
+    gen_s = time.perf_counter() - t0
+    dev, probs = [], []
+    for w in ws:
+        A = torch.from_numpy(np.ascontiguousarray(w.At_store)).cuda()
+        B = A.clone()   # a second buffer: B is read from its own memory
+        dev.append((A, B))
+        probs.append(cmm.problem(A, B, w.b, w.d, seed=w.seed, dtype=w.dtype, subtract_diag=True))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt = cmm.Batch(ctx, probs, autotune=True, keep=dev)
+    create_s = time.perf_counter() - t0
+
+    def step():
+        bt.run(asynchronous=True)
+        return [bt.sketch(q).topk(w.K, "upper") for q, w in enumerate(ws)]
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    graph_ms, graph_n = ctx.profile_read("batch")
+    dec_ms, _ = ctx.profile_read("decode")
+    ctx.profile(False)
+    ms = (t1 - t0) * 1e3 / steps
+    input_bytes = sum(2 * w.n1 * w.m * 2 for w in ws)
+    # the same products one after another through the standalone call
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for w, (A, B) in zip(ws, dev):
+        cmm.sketch_product(ctx, A, B, w.b, w.d, seed=w.seed, dtype=w.dtype,
+                           subtract_diag=True).free()
+    torch.cuda.synchronize()
+    alone_ms = (time.perf_counter() - t0) * 1e3
+    hits = sum(len({(int(min(a, c)), int(max(a, c))) for a, c in zip(oi, oj)}
+                   & {(int(min(p, q)), int(max(p, q))) for p, q in w.planted})
+               for w, (oi, oj, _) in zip(ws, res))
+    classes = sorted({(w.b, W.next_pow2(w.n1)) for w in ws})
+    out = {
+        "workload": "64 covariance products, n=m log-uniform in [512, 8192], b=next_pow2(8n), "
+                    "d=5, bf16, diagonal subtracted, top-(planted pairs) i<j each",
+        "value": round(input_bytes / (ms * 1e-3) / 1e9, 3), "unit": "GB/s",
+        "ms_per_step": round(ms, 4), "steps": steps, "warmup": warmup,
+        "graph_replay_ms": round(graph_ms / max(graph_n, 1), 4),
+        "topk_ms_per_step": round(dec_ms / max(steps, 1), 4),
+        "standalone_sequential_sketch_ms": round(alone_ms, 3),
+        "input_bytes": input_bytes, "products": len(ws), "size_classes": len(classes),
+        "tuning": {f"b={b},n<={n}": list(ctx.tuning(n, n, n, b, 5, "bf16")) for b, n in classes},
+        "create_s": round(create_s, 2), "generate_s": round(gen_s, 2),
+        "planted_recall": round(hits / sum(len(w.planted) for w in ws), 4),
+    }
+    if with_oracle:
+        from oracle import cmm_oracle as O
+        worst = 0.0
+        for q in sorted(range(len(ws)), key=lambda q: ws[q].n1)[:3]:
+            w = ws[q]
+            A, Bq = W.dequantised(w)
+            c_ref, _, _ = O.run(A, Bq, w.b, w.d, w.seed, subtract_diag=True)
+            c = bt.sketch(q).c()
+            worst = max(worst, max(float(np.linalg.norm(c[t] - c_ref[t]) / np.linalg.norm(c_ref[t]))
+                                   for t in range(w.d)))
+        out["max_rel_l2_c_vs_oracle_3_smallest"] = worst
+    bt.free()
+    return out
+
+
 def traffic_record(w):
     """HBM bytes per fft_mac launch from the committed rocprofv3 counter
     summary, if it was taken on this workload and the kernel source has not
@@ -152,6 +237,17 @@ def main():
 
     cmm.load()
     torch.cuda.init()
+    if args.workload == 5:
+        ctx = cmm.Context(0)
+        bres = run_batched(ctx, args.steps, args.warmup, not args.no_cpu)
+        ctx.close()
+        print(json.dumps({
+            "metric": METRIC, "value": bres["value"], "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": bres["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+            "data": "synthetic", "config": {"workload": bres["workload"]}, "batched_form": bres}),
+            flush=True)
+        return
     w = W.make_workload(args.workload, dtype=args.dtype)
     n1, m, n3, b, d, K = w.n1, w.m, w.n3, w.b, w.d, w.K
     ctx = cmm.Context(0)
@@ -218,6 +314,8 @@ def main():
         out["parity"]["planted_recall"] = planted_recall(w, oi, oj)
     if not args.no_compare and w.dtype == "f32" and w.mode != "column":
         out["bf16_same_workload"] = compare_bf16(ctx, args, w, c_ref, oi, oj, value)
+    if not args.no_batched:
+        out["batched_form"] = run_batched(ctx, max(3, args.steps // 4), 1, not args.no_cpu)
     sk.free()
     ctx.close()
     print(json.dumps(out), flush=True)
