@@ -38,10 +38,13 @@ namespace cmm {
 // with bits 4..7 (a bijection on [0, C)).
 __host__ __device__ __forceinline__ int fft_swizzle(int i) { return i ^ ((i >> 4) & 15); }
 
-// Fold entry of bucket u for an FFT row of length C = 1 << log2c: the
-// swizzled LDS slot of u mod C and the weight index u >> log2(C/16).
+// Fold entry of bucket u for an FFT row of length C = 1 << log2c, as two
+// byte offsets of 8-byte LDS elements: bits 0..15 hold 8 * (swizzled slot of
+// u mod C) (C <= 8192), bits 16..31 hold 8 * (weight index u >> log2(C/16)),
+// an index below 16 R <= 4096 for at most 256 rows.
 __host__ __device__ __forceinline__ uint32_t fold_entry(uint32_t u, int log2c) {
-  return ((u >> (log2c - 4)) << 16) | (uint32_t)fft_swizzle((int)(u & ((1u << log2c) - 1)));
+  return ((u >> (log2c - 4)) << 19) |
+         ((uint32_t)fft_swizzle((int)(u & ((1u << log2c) - 1))) << 3);
 }
 
 constexpr int kMaxLog2C = 13;          // FFT row length C <= 8192

@@ -147,7 +147,7 @@ __device__ __forceinline__ void fetch(Batch<kU>& bt, const float* sa, const uint
 // r = u mod C, q = u div C equals omega_b^(f1 j) * omega_16R^(f1 v) with
 // j = u mod T (the owning thread) and v = u div T; the first factor is
 // common to all slots of thread j and applied once per slot after the fold,
-// the second comes from the 16R-entry table w16.
+// the second comes from the block's 16R-entry table wf[v] = omega_16R^(f1 v).
 //
 // The fold adds in fixed point with LDS integer atomics (float LDS atomics
 // are an order of magnitude slower, and integer sums do not depend on the
@@ -160,39 +160,48 @@ __device__ __forceinline__ void fetch(Batch<kU>& bt, const float* sa, const uint
 __device__ __forceinline__ unsigned long long pack2(int re, int im) {
   return (unsigned long long)(((long long)im << 32) + (long long)re);
 }
+// p = im * 2^32 + re with re signed: the high word is im - [re < 0].
 __device__ __forceinline__ int2 unpack2(unsigned long long p) {
-  const int re = (int)(uint32_t)(p & 0xFFFFFFFFull);
-  const int im = (int)(long long)(((long long)p - (long long)re) >> 32);
-  return make_int2(re, im);
+  const uint32_t lo = (uint32_t)p, hi = (uint32_t)(p >> 32);
+  return make_int2((int)lo, (int)(hi + (lo >> 31)));
+}
+
+// LDS element at byte offset `off` (fold entries carry byte offsets).
+template <typename V> __device__ __forceinline__ V& at_byte(V* base, uint32_t off) {
+  return *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + off);
+}
+template <typename V> __device__ __forceinline__ const V& at_byte(const V* base, uint32_t off) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + off);
 }
 
 // The batch is folded in groups of 4 entries: a group that lies wholly past
 // the segment is skipped by a wave-uniform test; inside a group there is no
 // per-entry branch (so the weight reads issue together) and an invalid
-// entry (padding) adds 0 to the calling thread's own first slot.
-template <int L, int G, int kU>
-__device__ __forceinline__ void fold(const Batch<kU>& bt, unsigned long long* Z, int f1, int m16,
-                                     const float2* w16, float scale, int own_slot, int ls,
+// entry (padding) adds 0 to the calling thread's own first slot.  Row 0 has
+// unit weights (ROW0).
+template <int G, int kU, bool ROW0>
+__device__ __forceinline__ void fold(const Batch<kU>& bt, unsigned long long* Z,
+                                     const float2* wf, float scale, uint32_t own_off, int ls,
                                      int first) {
   static_assert(kU % 4 == 0, "groups of 4");
 #pragma unroll
   for (int g0 = 0; g0 < kU; g0 += 4) {
     if ((first + g0) * G >= ls) break;
     float2 w[4];
-    if (f1 != 0) {
+    if constexpr (!ROW0) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) w[i] = w16[(f1 * (int)(bt.u[g0 + i] >> 16)) & m16];
+      for (int i = 0; i < 4; ++i) w[i] = at_byte(wf, bt.u[g0 + i] >> 16);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const uint32_t e = bt.u[g0 + i];   // (u div T) << 16 | swizzled slot
+      const uint32_t e = bt.u[g0 + i];
       const bool ok = e != 0xFFFFFFFFu;
-      const int slot = ok ? (int)(e & 0xFFFFu) : own_slot;
+      const uint32_t off = ok ? (e & 0xFFFFu) : own_off;
       // |value * scale| < 2^30: float32 keeps 24 bits, so values near the top
       // have no fraction and truncation only touches the smallest ones
       const float sv = ok ? bt.v[g0 + i] * scale : 0.0f;
-      if (f1 == 0) atomicAdd(&Z[slot], (unsigned long long)(long long)(int)sv);
-      else atomicAdd(&Z[slot], pack2((int)(sv * w[i].x), (int)(sv * w[i].y)));
+      if constexpr (ROW0) atomicAdd(&at_byte(Z, off), (unsigned long long)(long long)(int)sv);
+      else atomicAdd(&at_byte(Z, off), pack2((int)(sv * w[i].x), (int)(sv * w[i].y)));
     }
   }
 }
@@ -205,7 +214,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   float2* P0 = lds;
   float2* P1 = lds + C;
   float2* tm = lds + 2 * C;
-  float2* w16 = tm + F::NMID;        // omega_16R^x, x < 16 R
+  float2* wf = tm + F::NMID;         // omega_16R^(f1 v), v < 16 R
   static_assert(F::S <= 4, "at most two middle stages");
 
   const int bid = blockIdx.x;
@@ -222,7 +231,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   const int ke = (int)((int64_t)a.m * (ks + 1) / a.KS);
 
   const int m16 = 16 * R - 1;
-  for (int q = j; q < 16 * R; q += T) w16[q] = a.tw[(int64_t)q * T];
+  for (int q = j; q < 16 * R; q += T) wf[q] = a.tw[(int64_t)((f1 * q) & m16) * T];
   const float2 sj = a.tw[((uint64_t)f1 * (uint64_t)j) & bm];   // omega_b^(f1 j)
   const int jbase = sw(j);
   // last-stage twiddles omega_C^((j mod Ns) r), Ns = span(S-1)
@@ -276,10 +285,19 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) Z[own<T>(jbase, j, q)] = 0ull;
       __builtin_amdgcn_wave_barrier();
-      fold<L, G, kU>(bt, Z, f1, m16, w16, scale, jbase, ls, 0);
-      for (int first = kU; first * G < ls; first += kU) {
-        fetch<G, kU>(bt, sa, en, ls, lane, first);
-        fold<L, G, kU>(bt, Z, f1, m16, w16, scale, jbase, ls, first);
+      const uint32_t own_off = (uint32_t)jbase * 8u;
+      if (f1 == 0) {
+        fold<G, kU, true>(bt, Z, wf, scale, own_off, ls, 0);
+        for (int first = kU; first * G < ls; first += kU) {
+          fetch<G, kU>(bt, sa, en, ls, lane, first);
+          fold<G, kU, true>(bt, Z, wf, scale, own_off, ls, first);
+        }
+      } else {
+        fold<G, kU, false>(bt, Z, wf, scale, own_off, ls, 0);
+        for (int first = kU; first * G < ls; first += kU) {
+          fetch<G, kU>(bt, sa, en, ls, lane, first);
+          fold<G, kU, false>(bt, Z, wf, scale, own_off, ls, first);
+        }
       }
       // first batch of the next (side, k), in flight during the transform
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0);
