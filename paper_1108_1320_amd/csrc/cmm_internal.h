@@ -7,8 +7,8 @@
 //   hs[side][t][x]        int32  (h(x) << 1) | (s(x) == -1)
 //   cnt[side][t][u]       int32  members of bucket u (u < b)
 //   pos[side][t][u]       int32  layout position of non-empty bucket u, -1 if empty
-//   ent[side][t][p]       uint32 FFT fold entry of position p: (u div T) << 16 | fold_slot(u)
-//                                (0xFFFFFFFF = padding)
+//   ent[side][t][p]       uint32 FFT fold entry of position p: 8 (u div T) << 16 | 8 fold_slot(u)
+//                                (padding: an own slot of the segment's wave, weight index 0)
 //   tab[side][t][p]       uint32 first member | sign << 31 | more-members << 30
 //   SA[side][t][k][p]     float  count sketch of column k (side 0) / row k (side 1)
 //   colmax[side][t][k]    float  max |SA[side][t][k][.]| (fixed-point scale of the fold)
@@ -26,7 +26,6 @@
 #include <stdint.h>
 
 #define CMM_P61 0x1FFFFFFFFFFFFFFFull
-#define CMM_PAD_ENT 0xFFFFFFFFu
 #define CMM_PAD_TAB 0xFFFFFFFFu
 #define CMM_TAB_NEG 0x80000000u
 #define CMM_TAB_MORE 0x40000000u
@@ -45,6 +44,15 @@ __host__ __device__ __forceinline__ int fft_swizzle(int i) { return i ^ ((i >> 4
 __host__ __device__ __forceinline__ uint32_t fold_entry(uint32_t u, int log2c) {
   return ((u >> (log2c - 4)) << 19) |
          ((uint32_t)fft_swizzle((int)(u & ((1u << log2c) - 1))) << 3);
+}
+
+// Fold entry of padding position r of layout segment w (G lanes per
+// segment): the first own slot of the lane that folds position r (lane
+// r mod G), with weight index 0.  The count sketch stores 0 at padding
+// positions, so folding one adds 0 to a slot of the folding lane itself
+// (distinct lanes, distinct LDS addresses).
+__host__ __device__ __forceinline__ uint32_t pad_entry(int w, int G, int r) {
+  return (uint32_t)fft_swizzle(w * G + r % G) << 3;
 }
 
 constexpr int kMaxLog2C = 13;          // FFT row length C <= 8192

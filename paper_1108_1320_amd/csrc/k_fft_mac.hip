@@ -132,14 +132,15 @@ template <int U> struct Batch {
   uint32_t u[U];
 };
 
+// Past the segment's end a lane gets value 0 and its own first slot.
 template <int G, int kU>
 __device__ __forceinline__ void fetch(Batch<kU>& bt, const float* sa, const uint32_t* en, int ls,
-                                      int lane, int first) {
+                                      int lane, int first, uint32_t own_off) {
 #pragma unroll
   for (int i = 0; i < kU; ++i) {
     const int it = lane + G * (first + i);
     if (it < ls) { bt.v[i] = sa[it]; bt.u[i] = en[it]; }
-    else { bt.v[i] = 0.0f; bt.u[i] = 0xFFFFFFFFu; }
+    else { bt.v[i] = 0.0f; bt.u[i] = own_off; }
   }
 }
 
@@ -176,13 +177,11 @@ template <typename V> __device__ __forceinline__ const V& at_byte(const V* base,
 
 // The batch is folded in groups of 4 entries: a group that lies wholly past
 // the segment is skipped by a wave-uniform test; inside a group there is no
-// per-entry branch (so the weight reads issue together) and an invalid
-// entry (padding) adds 0 to the calling thread's own first slot.  Row 0 has
-// unit weights (ROW0).
+// branch, so the weight reads issue together.  Padding entries carry value 0
+// and an own slot of the wave.  Row 0 has unit weights (ROW0).
 template <int G, int kU, bool ROW0>
 __device__ __forceinline__ void fold(const Batch<kU>& bt, unsigned long long* Z,
-                                     const float2* wf, float scale, uint32_t own_off, int ls,
-                                     int first) {
+                                     const float2* wf, float scale, int ls, int first) {
   static_assert(kU % 4 == 0, "groups of 4");
 #pragma unroll
   for (int g0 = 0; g0 < kU; g0 += 4) {
@@ -194,12 +193,10 @@ __device__ __forceinline__ void fold(const Batch<kU>& bt, unsigned long long* Z,
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const uint32_t e = bt.u[g0 + i];
-      const bool ok = e != 0xFFFFFFFFu;
-      const uint32_t off = ok ? (e & 0xFFFFu) : own_off;
+      const uint32_t off = bt.u[g0 + i] & 0xFFFFu;
       // |value * scale| < 2^30: float32 keeps 24 bits, so values near the top
       // have no fraction and truncation only touches the smallest ones
-      const float sv = ok ? bt.v[g0 + i] * scale : 0.0f;
+      const float sv = bt.v[g0 + i] * scale;
       if constexpr (ROW0) atomicAdd(&at_byte(Z, off), (unsigned long long)(long long)(int)sv);
       else atomicAdd(&at_byte(Z, off), pack2((int)(sv * w[i].x), (int)(sv * w[i].y)));
     }
@@ -265,8 +262,9 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   const float* cm1 = a.cmax1 + (int64_t)t * a.m;
   unsigned long long* Z = reinterpret_cast<unsigned long long*>(P0);
 
+  const uint32_t own_off = (uint32_t)jbase * 8u;
   Batch<kU> bt;
-  if (kb < ke) fetch<G, kU>(bt, sa0 + (int64_t)kb * a.Lrow0, en0, ls0, lane, 0);
+  if (kb < ke) fetch<G, kU>(bt, sa0 + (int64_t)kb * a.Lrow0, en0, ls0, lane, 0, own_off);
 
   for (int k = kb; k < ke; ++k) {
     float2 X[16];
@@ -285,23 +283,22 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) Z[own<T>(jbase, j, q)] = 0ull;
       __builtin_amdgcn_wave_barrier();
-      const uint32_t own_off = (uint32_t)jbase * 8u;
       if (f1 == 0) {
-        fold<G, kU, true>(bt, Z, wf, scale, own_off, ls, 0);
+        fold<G, kU, true>(bt, Z, wf, scale, ls, 0);
         for (int first = kU; first * G < ls; first += kU) {
-          fetch<G, kU>(bt, sa, en, ls, lane, first);
-          fold<G, kU, true>(bt, Z, wf, scale, own_off, ls, first);
+          fetch<G, kU>(bt, sa, en, ls, lane, first, own_off);
+          fold<G, kU, true>(bt, Z, wf, scale, ls, first);
         }
       } else {
-        fold<G, kU, false>(bt, Z, wf, scale, own_off, ls, 0);
+        fold<G, kU, false>(bt, Z, wf, scale, ls, 0);
         for (int first = kU; first * G < ls; first += kU) {
-          fetch<G, kU>(bt, sa, en, ls, lane, first);
-          fold<G, kU, false>(bt, Z, wf, scale, own_off, ls, first);
+          fetch<G, kU>(bt, sa, en, ls, lane, first, own_off);
+          fold<G, kU, false>(bt, Z, wf, scale, ls, first);
         }
       }
       // first batch of the next (side, k), in flight during the transform
-      if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0);
-      else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0);
+      if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
+      else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0, own_off);
       __builtin_amdgcn_wave_barrier();
       if (f1 != 0) {
         const float2 sjs = make_float2(sj.x * inv, sj.y * inv);

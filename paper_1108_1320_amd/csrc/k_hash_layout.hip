@@ -184,7 +184,7 @@ __global__ __launch_bounds__(1024) void k_layout_finish(int W, int G, int Lcap, 
   for (int w = 0; w < W; ++w) {
     int sc = min(segcount[t * W + w], Lcap);
     for (int r = sc + tid; r < L; r += blockDim.x) {
-      ent_t[w * Lcap + r] = CMM_PAD_ENT;
+      ent_t[w * Lcap + r] = pad_entry(w, G, r);
       tab_t[w * Lcap + r] = CMM_PAD_TAB;
       cntp_t[w * Lcap + r] = 0;
     }
