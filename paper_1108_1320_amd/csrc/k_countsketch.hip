@@ -58,23 +58,28 @@ template <> struct Elem<2> {      // fp8 e4m3fn bits
 // like the integers), one barrier per row.
 constexpr int kCsThreads = 512;
 
-template <int DT, bool VEC>
+template <int DT>
 __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, int m, int W, int kblock) {
   extern __shared__ float row[];
   __shared__ uint32_t smax[2][64];
   typedef Elem<DT> E;
+  typedef typename E::S S;
   const int tid = threadIdx.x;
   const int n = sd.n;
   const int k0 = blockIdx.x * kblock;
   const int k1 = min(m, k0 + kblock);
-  const typename E::S* X = (const typename E::S*)sd.X;
+  const S* X = (const S*)sd.X;
+  const bool scale16 = sd.scale == nullptr || (uintptr_t)sd.scale % 16 == 0;
   if (tid < 128) smax[tid >> 6][tid & 63] = 0u;
   int par = 0;
   for (int k = k0; k < k1; ++k, par ^= 1) {
-    const typename E::S* xr = X + (int64_t)k * sd.ld;
-    if (VEC) {
-      const typename E::V4* xv = (const typename E::V4*)xr;
-      const int n4 = n >> 2;
+    const S* xr = X + (int64_t)k * sd.ld;
+    // the row's first `head` elements are staged one by one, the body four at
+    // a time from an address aligned to four elements, then the tail
+    const int head = min(n, (int)((4 - ((uintptr_t)xr / sizeof(S)) % 4) % 4));
+    const int n4 = (n - head) >> 2;
+    const typename E::V4* xv = (const typename E::V4*)(xr + head);
+    if (head == 0 && scale16) {
       for (int q = tid; q < n4; q += kCsThreads) {
         float o[4];
         E::four(xv[q], o);
@@ -84,12 +89,18 @@ __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, 
         }
         *(float4*)&row[4 * q] = make_float4(o[0], o[1], o[2], o[3]);
       }
-      for (int x = 4 * n4 + tid; x < n; x += kCsThreads)
-        row[x] = E::one(xr[x]) * (sd.scale ? sd.scale[x] : 1.0f);
     } else {
-      for (int x = tid; x < n; x += kCsThreads)
-        row[x] = E::one(xr[x]) * (sd.scale ? sd.scale[x] : 1.0f);
+      for (int q = tid; q < n4; q += kCsThreads) {
+        float o[4];
+        E::four(xv[q], o);
+        const int x = head + 4 * q;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) row[x + i] = o[i] * (sd.scale ? sd.scale[x + i] : 1.0f);
+      }
     }
+    if (tid < head) row[tid] = E::one(xr[tid]) * (sd.scale ? sd.scale[tid] : 1.0f);
+    for (int x = head + 4 * n4 + tid; x < n; x += kCsThreads)
+      row[x] = E::one(xr[x]) * (sd.scale ? sd.scale[x] : 1.0f);
     __syncthreads();
     for (int t = 0; t < d; ++t) {
       const int L = sd.lseg[t];
@@ -140,21 +151,16 @@ __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, 
 }
 
 hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStream_t s) {
-  const int esz = dtype == 0 ? 4 : (dtype == 1 ? 2 : 1);
-  const bool vec = (sd.n % 4 == 0) && (sd.ld % 4 == 0) &&
-                   ((uintptr_t)sd.X % (4 * esz) == 0) &&
-                   (sd.scale == nullptr || (uintptr_t)sd.scale % 16 == 0);
   int kblock = (int)((int64_t)g.m / std::max(1, g.cs_blocks));
   if (kblock < 1) kblock = 1;
   const int blocks = (g.m + kblock - 1) / kblock;
   const size_t lds = (size_t)sd.n * sizeof(float);
-#define CMM_CS(DTV, VV)                                                                     \
-  hipLaunchKernelGGL((k_countsketch<DTV, VV>), dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, \
-                     g.W, kblock)
-  if (dtype == 0) { if (vec) CMM_CS(0, true); else CMM_CS(0, false); }
-  else if (dtype == 1) { if (vec) CMM_CS(1, true); else CMM_CS(1, false); }
-  else { if (vec) CMM_CS(2, true); else CMM_CS(2, false); }
-#undef CMM_CS
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_countsketch<0>, dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock);
+  else if (dtype == 1)
+    hipLaunchKernelGGL(k_countsketch<1>, dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock);
+  else
+    hipLaunchKernelGGL(k_countsketch<2>, dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock);
   return hipGetLastError();
 }
 
@@ -162,12 +168,9 @@ hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStr
 // row of up to 24576 floats needs (done once per context, outside any graph
 // capture).
 hipError_t prepare_countsketch() {
-  const void* fns[] = {reinterpret_cast<const void*>(&k_countsketch<0, true>),
-                       reinterpret_cast<const void*>(&k_countsketch<0, false>),
-                       reinterpret_cast<const void*>(&k_countsketch<1, true>),
-                       reinterpret_cast<const void*>(&k_countsketch<1, false>),
-                       reinterpret_cast<const void*>(&k_countsketch<2, true>),
-                       reinterpret_cast<const void*>(&k_countsketch<2, false>)};
+  const void* fns[] = {reinterpret_cast<const void*>(&k_countsketch<0>),
+                       reinterpret_cast<const void*>(&k_countsketch<1>),
+                       reinterpret_cast<const void*>(&k_countsketch<2>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     if (e != hipSuccess) return e;

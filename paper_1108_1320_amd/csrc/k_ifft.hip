@@ -166,13 +166,21 @@ __global__ void k_diag_partial(const void* A, int64_t lda, const float* sA, cons
   partial[(int64_t)kc * n + i] = acc;
 }
 
-__global__ void k_diag_reduce(const double* __restrict__ partial, int n, int kchunks,
-                              double* __restrict__ diag) {
+// Sum of the k-chunk partials of entry i: eight independent running sums
+// (chunk kc goes to sum kc mod 8) keep eight loads in flight, and are added
+// in a fixed order, so the result does not depend on timing.
+__global__ __launch_bounds__(64) void k_diag_reduce(const double* __restrict__ partial, int n,
+                                                    int kchunks, double* __restrict__ diag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double s = 0.0;
-  for (int kc = 0; kc < kchunks; ++kc) s += partial[(int64_t)kc * n + i];
-  diag[i] = s;
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int kc = 0;
+  for (; kc + 8 <= kchunks; kc += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s[q] += partial[(int64_t)(kc + q) * n + i];
+  }
+  for (int q = 0; kc + q < kchunks; ++q) s[q] += partial[(int64_t)(kc + q) * n + i];
+  diag[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 hipError_t launch_diag(int dtype, const SideDesc& a, const SideDesc& bs, int m, int n,
@@ -186,7 +194,7 @@ hipError_t launch_diag(int dtype, const SideDesc& a, const SideDesc& bs, int m, 
     hipLaunchKernelGGL(k_diag_partial<2>, grid, dim3(256), 0, s, a.X, a.ld, a.scale, bs.X, bs.ld, bs.scale, m, n, kchunks, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_diag_reduce, dim3((n + 255) / 256), dim3(256), 0, s, partial, n, kchunks, diag);
+  hipLaunchKernelGGL(k_diag_reduce, dim3((n + 63) / 64), dim3(64), 0, s, partial, n, kchunks, diag);
   return hipGetLastError();
 }
 
