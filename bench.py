@@ -58,9 +58,12 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5])
     p.add_argument("--dtype", default=None, help="override the workload's dtype (f32/bf16/fp8)")
+    p.add_argument("--d", type=int, default=None, help="override the number of repetitions")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-compare", action="store_true", help="skip the bf16 run of the same workload")
     p.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="use the built-in geometry instead of tuning the size class first")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -249,8 +252,17 @@ def main():
             flush=True)
         return
     w = W.make_workload(args.workload, dtype=args.dtype)
+    if args.d is not None:
+        w.d = args.d
     n1, m, n3, b, d, K = w.n1, w.m, w.n3, w.b, w.d, w.K
     ctx = cmm.Context(0)
+    tuned = None
+    if not args.no_autotune:
+        # the library's one-time tuning of this size class (cached in the context)
+        t0 = time.perf_counter()
+        tu, tms = ctx.autotune(n1, m, n3, b, d, w.dtype)
+        tuned = {"log2c_kmax_csblocks": list(tu), "product_ms": round(tms, 4),
+                 "seconds": round(time.perf_counter() - t0, 2)}
     r = run_timed(ctx, w, args.steps, args.warmup)
     ms, kern, input_bytes = r["ms"], r["kern"], r["input_bytes"]
     sk, (oi, oj, ov) = r["sketch"], r["topk"]
@@ -285,7 +297,9 @@ def main():
                          f"{w.name} n1={n1} m={m} n3={n3} b={b} d={d} top-{K} {w.mode}"),
             "n1": n1, "m": m, "n3": n3, "b": b, "d": d, "K": K, "topk_mode": w.mode,
             "input_bytes": input_bytes,
+            "geometry": list(ctx.tuning(n1, m, n3, b, d, w.dtype)),
         },
+        "autotune": tuned,
         "hbm_frac": round(value / HBM_PEAK_GBPS, 5),
         "input_elements_per_s": round((n1 * m + m * n3) / (ms * 1e-3), 1),
         "nominal_fft_gflops": round(flop / (ms * 1e-3) / 1e9, 1),
@@ -331,6 +345,8 @@ def compare_bf16(ctx, args, w32, c_ref, oi32, oj32, value32):
     w = W.Workload(name=w32.name, n1=w32.n1, m=w32.m, n3=w32.n3, b=w32.b, d=w32.d, K=w32.K,
                    dtype="bf16", mode=w32.mode, seed=w32.seed, subtract_diag=w32.subtract_diag,
                    At_store=store, B_store=store, planted=w32.planted, same_operand=True)
+    if not args.no_autotune:
+        ctx.autotune(w.n1, w.m, w.n3, w.b, w.d, "bf16")
     r = run_timed(ctx, w, max(5, args.steps // 2), 2)
     v = r["input_bytes"] / (r["ms"] * 1e-3) / 1e9
     c16 = r["sketch"].c()
@@ -341,10 +357,20 @@ def compare_bf16(ctx, args, w32, c_ref, oi32, oj32, value32):
            "element_rate_vs_f32": round((v / 2.0) / (value32 / 4.0), 4),
            "topk_overlap_with_f32": round(len(both) / w.K, 4),
            "planted_recall": planted_recall(w, oi, oj),
+           "geometry": list(ctx.tuning(w.n1, w.m, w.n3, w.b, w.d, "bf16")),
            "kernel_ms_per_step": {k: round(x[0] / max(x[1], 1), 4) for k, x in r["kern"].items()}}
     if c_ref is not None:
-        res["max_rel_l2_c_vs_f64_oracle_of_f32_operands"] = max(
-            float(np.linalg.norm(c16[t] - c_ref[t]) / np.linalg.norm(c_ref[t])) for t in range(w.d))
+        from oracle import cmm_oracle as O
+        A16, B16 = W.dequantised(w)
+        c_ref16, _, _ = O.run(A16, B16, w.b, w.d, w.seed, subtract_diag=w.subtract_diag)
+
+        def rel(x, y):
+            return max(float(np.linalg.norm(x[t] - y[t]) / np.linalg.norm(y[t])) for t in range(w.d))
+        # total = GPU bf16 vs oracle(f32 values); arithmetic = GPU bf16 vs oracle(bf16 values);
+        # quantisation = oracle(bf16 values) vs oracle(f32 values)
+        res["max_rel_l2_c_vs_f64_oracle_of_f32_operands"] = rel(c16, c_ref)
+        res["max_rel_l2_c_arithmetic"] = rel(c16, c_ref16)
+        res["max_rel_l2_c_quantisation"] = rel(c_ref16, c_ref)
     r["sketch"].free()
     return res
 

@@ -84,11 +84,13 @@ struct SideDesc {
 // Launch-shape choices of one product (picked by the autotuner or defaults):
 // FFT row length 2^log2c (its radix sequence: 2^(log2c mod 4) then 16s),
 // at most kmax values of k per FFT block (the float32 partial-sum length),
-// and the number of countsketch blocks.
+// and the number of countsketch blocks.  The defaults are the autotuner's
+// choice for the covariance and transform workloads with n = 4096..16384
+// measured on gfx950.
 struct Tuning {
   int log2c = 12;
-  int kmax = 128;
-  int cs_blocks = 2048;
+  int kmax = 32;
+  int cs_blocks = 4096;
 };
 
 struct Geometry {
