@@ -1119,48 +1119,106 @@ int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int6
                              : [&] { int64_t t = 0; for (int64_t i = 0; i < sk->n1; ++i) t += std::max<int64_t>(0, sk->n3 - i - 1); return t; }();
   if (K > domain) return fail(c, CMM_EINVAL, "K larger than the candidate domain");
   if (K > cmm::kTopkCap / 2) return fail(c, CMM_EUNSUPPORTED, "K above 2048");
+  constexpr int kWide = 16384;   // candidates kept by the fused histogram + collect pass
   uint32_t* hist = w.get<uint32_t>(4096);
-  uint32_t* count = w.get<uint32_t>(1);
+  uint32_t* count = w.get<uint32_t>(2);
+  cmm::TopkCand* wide = w.get<cmm::TopkCand>(kWide);
   cmm::TopkCand* cand = w.get<cmm::TopkCand>(cmm::kTopkCap);
   int64_t* oi = w.get<int64_t>(K);
   int64_t* oj = w.get<int64_t>(K);
   float* ov = w.get<float>(K);
-  if (!hist || !count || !cand || !oi || !oj || !ov) return fail(c, CMM_ENOMEM, "workspace allocation failed");
+  if (!hist || !count || !wide || !cand || !oi || !oj || !ov)
+    return fail(c, CMM_ENOMEM, "workspace allocation failed");
   std::vector<uint32_t> h(4096);
-  // digit passes: bits [30:19], [18:7], [6:0]
-  const int dshift[3] = {19, 7, 0};
-  const uint32_t dmask[3] = {0xFFF, 0xFFF, 0x7F};
-  uint32_t prefix = 0;
-  int pshift = 32;
-  int64_t above = 0;
-  int64_t need = K;
-  uint32_t thresh = 0;
-  bool done = false;
+  const int tiles = (int)((sk->n1 + 15) / 16);
   {
     Scope sc_(c, "decode");
-    for (int level = 0; level < 3 && !done; ++level) {
+    // Fast path: a pass over every 16th row tile estimates a threshold T0
+    // above which about 2K + 64 estimates lie; one full pass then builds the
+    // exact histogram of the top 12 key bits and keeps every candidate with
+    // key >= T0.  The exact histogram shows whether T0 is at or below the
+    // K-th key and whether the kept set is complete; otherwise the
+    // digit-by-digit passes below run (from the histogram already built).
+    bool have_level0 = false, done = false;
+    if (tiles >= 64) {
       CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
-      CMM_HIP(c, cmm::launch_topk_hist(dd, mode, prefix, pshift, dshift[level], dmask[level], hist, s));
+      CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 16, 0, 32, 19, 0xFFF, hist, 0, nullptr, nullptr, 0, s));
       CMM_HIP(c, hipMemcpyAsync(h.data(), hist, 4096 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
       CMM_HIP(c, hipStreamSynchronize(s));
-      int64_t cum = 0;
-      int bin = -1;
-      for (int q = (int)dmask[level]; q >= 0; --q) {
-        if (cum + h[q] >= need) { bin = q; break; }
-        cum += h[q];
+      int64_t sampled = 0;
+      for (uint32_t x : h) sampled += x;
+      int b0 = -1;
+      if (sampled > 0) {
+        const double want = (2.0 * K + 64.0) * (double)sampled / (double)domain;
+        int64_t cum = 0;
+        for (int q = 4095; q >= 0; --q) {
+          cum += h[q];
+          if (cum >= 8 && (double)cum >= want) { b0 = q; break; }
+        }
       }
-      if (bin < 0) return fail(c, CMM_EHIP, "top-K histogram lost entries");
-      prefix |= (uint32_t)bin << dshift[level];
-      const int64_t total = above + cum + h[bin];
-      if (total <= cmm::kTopkCap) { thresh = prefix; done = true; break; }
-      above += cum;
-      need -= cum;
-      pshift = dshift[level];
+      if (b0 >= 0) {
+        const uint32_t T0 = (uint32_t)b0 << 19;
+        CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
+        CMM_HIP(c, cmm::launch_fill_i32((int32_t*)count, 2, 0, s));
+        CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 1, 0, 32, 19, 0xFFF, hist, T0, wide, count, kWide, s));
+        CMM_HIP(c, hipMemcpyAsync(h.data(), hist, 4096 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        CMM_HIP(c, hipStreamSynchronize(s));
+        have_level0 = true;
+        int64_t n0 = 0;
+        for (int q = b0; q < 4096; ++q) n0 += h[q];
+        if (n0 >= K && n0 <= kWide) {
+          int64_t cum = 0;
+          int bk = 4095;
+          for (; bk >= 0; --bk) { cum += h[bk]; if (cum >= K) break; }
+          if (n0 <= cmm::kTopkCap) {
+            CMM_HIP(c, cmm::launch_topk_final(wide, count, cmm::kTopkCap, K, (int)sk->n3, oi, oj, ov, s));
+            done = true;
+          } else if (cum <= cmm::kTopkCap) {
+            CMM_HIP(c, cmm::launch_topk_filter(wide, count, kWide, (uint32_t)bk << 19, cand, count + 1,
+                                               cmm::kTopkCap, s));
+            CMM_HIP(c, cmm::launch_topk_final(cand, count + 1, cmm::kTopkCap, K, (int)sk->n3, oi, oj, ov, s));
+            done = true;
+          }
+        }
+      }
     }
-    if (!done) return fail(c, CMM_EUNSUPPORTED, "more than 4096 estimates tie at the K-th magnitude");
-    CMM_HIP(c, cmm::launch_fill_i32((int32_t*)count, 1, 0, s));
-    CMM_HIP(c, cmm::launch_topk_collect(dd, mode, thresh, cand, count, cmm::kTopkCap, s));
-    CMM_HIP(c, cmm::launch_topk_final(cand, count, cmm::kTopkCap, K, (int)sk->n3, oi, oj, ov, s));
+    if (!done) {
+      // digit passes: bits [30:19], [18:7], [6:0]
+      const int dshift[3] = {19, 7, 0};
+      const uint32_t dmask[3] = {0xFFF, 0xFFF, 0x7F};
+      uint32_t prefix = 0;
+      int pshift = 32;
+      int64_t above = 0;
+      int64_t need = K;
+      uint32_t thresh = 0;
+      bool found = false;
+      for (int level = 0; level < 3 && !found; ++level) {
+        if (!(level == 0 && have_level0)) {
+          CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
+          CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 1, prefix, pshift, dshift[level], dmask[level], hist,
+                                           0, nullptr, nullptr, 0, s));
+          CMM_HIP(c, hipMemcpyAsync(h.data(), hist, 4096 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+          CMM_HIP(c, hipStreamSynchronize(s));
+        }
+        int64_t cum = 0;
+        int bin = -1;
+        for (int q = (int)dmask[level]; q >= 0; --q) {
+          if (cum + h[q] >= need) { bin = q; break; }
+          cum += h[q];
+        }
+        if (bin < 0) return fail(c, CMM_EHIP, "top-K histogram lost entries");
+        prefix |= (uint32_t)bin << dshift[level];
+        const int64_t total = above + cum + h[bin];
+        if (total <= cmm::kTopkCap) { thresh = prefix; found = true; break; }
+        above += cum;
+        need -= cum;
+        pshift = dshift[level];
+      }
+      if (!found) return fail(c, CMM_EUNSUPPORTED, "more than 4096 estimates tie at the K-th magnitude");
+      CMM_HIP(c, cmm::launch_fill_i32((int32_t*)count, 1, 0, s));
+      CMM_HIP(c, cmm::launch_topk_collect(dd, mode, thresh, cand, count, cmm::kTopkCap, s));
+      CMM_HIP(c, cmm::launch_topk_final(cand, count, cmm::kTopkCap, K, (int)sk->n3, oi, oj, ov, s));
+    }
   }
   CMM_HIP(c, hipMemcpyAsync(out_i, oi, sizeof(int64_t) * K, hipMemcpyDeviceToHost, s));
   CMM_HIP(c, hipMemcpyAsync(out_j, oj, sizeof(int64_t) * K, hipMemcpyDeviceToHost, s));

@@ -147,8 +147,13 @@ struct TopkCand {
 
 hipError_t launch_estimate(const DecodeDesc& dd, const int64_t* qi, const int64_t* qj, int64_t q,
                            float* out, hipStream_t s);
-hipError_t launch_topk_hist(const DecodeDesc& dd, int mode, uint32_t prefix, int prefix_shift,
-                            int digit_shift, uint32_t digit_mask, uint32_t* hist, hipStream_t s);
+hipError_t launch_topk_hist(const DecodeDesc& dd, int mode, int tile_stride, uint32_t prefix,
+                            int prefix_shift, int digit_shift, uint32_t digit_mask, uint32_t* hist,
+                            uint32_t thresh, TopkCand* cand, uint32_t* count, int cap,
+                            hipStream_t s);
+hipError_t launch_topk_filter(const TopkCand* in, const uint32_t* in_count, int in_cap,
+                              uint32_t thresh, TopkCand* out, uint32_t* out_count, int out_cap,
+                              hipStream_t s);
 hipError_t launch_topk_collect(const DecodeDesc& dd, int mode, uint32_t thresh, TopkCand* cand,
                                uint32_t* count, int cap, hipStream_t s);
 hipError_t launch_topk_final(const TopkCand* cand, const uint32_t* count, int cap, int K, int n3,

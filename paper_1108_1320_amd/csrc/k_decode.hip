@@ -88,14 +88,20 @@ __device__ __forceinline__ bool in_domain(int mode, int i, int j, int n1, int n3
   return i < n1 && j < n3 && (mode != 1 || i < j);
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void k_topk_hist(DecodeDesc dd, int mode, uint32_t pmask,
-                                                   uint32_t prefix, int dshift, uint32_t dmask,
-                                                   uint32_t* __restrict__ hist) {
+// Histogram of one key digit over the candidates whose key matches
+// `prefix` under `pmask`, over every tile_stride-th tile of 16 rows (1 = the
+// whole domain).  With COLLECT, candidates with key >= thresh are also
+// appended to `cand` (at most `cap`; `count` keeps counting past it).
+template <int D, bool COLLECT>
+__global__ __launch_bounds__(256) void k_topk_hist(DecodeDesc dd, int mode, int tile_stride,
+                                                   uint32_t pmask, uint32_t prefix, int dshift,
+                                                   uint32_t dmask, uint32_t* __restrict__ hist,
+                                                   uint32_t thresh, TopkCand* __restrict__ cand,
+                                                   uint32_t* __restrict__ count, int cap) {
   __shared__ uint32_t h[4096];
   const int tid = threadIdx.x;
   const int j = blockIdx.x * 256 + tid;
-  const int i0 = blockIdx.y * kTI;
+  const int i0 = blockIdx.y * tile_stride * kTI;
   if (mode == 1 && i0 >= (int)(blockIdx.x * 256 + 255)) return;   // tile below the diagonal
   for (int q = tid; q < 4096; q += 256) h[q] = 0;
   __syncthreads();
@@ -107,13 +113,38 @@ __global__ __launch_bounds__(256) void k_topk_hist(DecodeDesc dd, int mode, uint
       if (!in_domain(mode, i, j, dd.n1, dd.n3)) continue;
       HashVec<D> h1;
       load_hash<D>(h1, dd.hs1, dd.n1, i, dd.d);
-      const uint32_t key = __float_as_uint(fabsf(estimate<D>(dd, h1.v, h2.v, dd.d)));
+      const float est = estimate<D>(dd, h1.v, h2.v, dd.d);
+      const uint32_t key = __float_as_uint(fabsf(est));
       if ((key & pmask) == prefix) atomicAdd(&h[(key >> dshift) & dmask], 1u);
+      if constexpr (COLLECT) {
+        if (key >= thresh) {
+          const uint32_t slot = atomicAdd(count, 1u);
+          if (slot < (uint32_t)cap) {
+            TopkCand c; c.key = key; c.i = i; c.j = j; c.val = est;
+            cand[slot] = c;
+          }
+        }
+      }
     }
   }
   __syncthreads();
   for (int q = tid; q < 4096; q += 256)
     if (h[q]) atomicAdd(&hist[q], h[q]);
+}
+
+// Keep the candidates with key >= thresh (order not kept).
+__global__ void k_topk_filter(const TopkCand* __restrict__ in, const uint32_t* __restrict__ in_count,
+                              int in_cap, uint32_t thresh, TopkCand* __restrict__ out,
+                              uint32_t* __restrict__ out_count, int out_cap) {
+  const uint32_t c = *in_count;
+  const int n = (int)(c < (uint32_t)in_cap ? c : (uint32_t)in_cap);
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    const TopkCand e = in[q];
+    if (e.key >= thresh) {
+      const uint32_t slot = atomicAdd(out_count, 1u);
+      if (slot < (uint32_t)out_cap) out[slot] = e;
+    }
+  }
 }
 
 template <int D>
@@ -258,13 +289,30 @@ hipError_t launch_estimate(const DecodeDesc& dd, const int64_t* qi, const int64_
   return hipGetLastError();
 }
 
-hipError_t launch_topk_hist(const DecodeDesc& dd, int mode, uint32_t prefix, int prefix_shift,
-                            int digit_shift, uint32_t digit_mask, uint32_t* hist, hipStream_t s) {
+hipError_t launch_topk_hist(const DecodeDesc& dd, int mode, int tile_stride, uint32_t prefix,
+                            int prefix_shift, int digit_shift, uint32_t digit_mask, uint32_t* hist,
+                            uint32_t thresh, TopkCand* cand, uint32_t* count, int cap,
+                            hipStream_t s) {
   const uint32_t pmask = prefix_shift >= 32 ? 0u : ~((1u << prefix_shift) - 1u);
-  dim3 grid((dd.n3 + 255) / 256, (dd.n1 + kTI - 1) / kTI);
-#define CMM_H(DV) hipLaunchKernelGGL(k_topk_hist<DV>, grid, dim3(256), 0, s, dd, mode, pmask, prefix & pmask, digit_shift, digit_mask, hist)
-  CMM_DISPATCH_D(dd.d, CMM_H)
+  const int tiles = (dd.n1 + kTI - 1) / kTI;
+  dim3 grid((dd.n3 + 255) / 256, (tiles + tile_stride - 1) / tile_stride);
+  if (cand) {
+#define CMM_H(DV) hipLaunchKernelGGL((k_topk_hist<DV, true>), grid, dim3(256), 0, s, dd, mode, tile_stride, pmask, prefix & pmask, digit_shift, digit_mask, hist, thresh, cand, count, cap)
+    CMM_DISPATCH_D(dd.d, CMM_H)
 #undef CMM_H
+  } else {
+#define CMM_H(DV) hipLaunchKernelGGL((k_topk_hist<DV, false>), grid, dim3(256), 0, s, dd, mode, tile_stride, pmask, prefix & pmask, digit_shift, digit_mask, hist, 0u, (TopkCand*)nullptr, (uint32_t*)nullptr, 0)
+    CMM_DISPATCH_D(dd.d, CMM_H)
+#undef CMM_H
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_topk_filter(const TopkCand* in, const uint32_t* in_count, int in_cap,
+                              uint32_t thresh, TopkCand* out, uint32_t* out_count, int out_cap,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_topk_filter, dim3(grid1(in_cap)), dim3(256), 0, s, in, in_count, in_cap,
+                     thresh, out, out_count, out_cap);
   return hipGetLastError();
 }
 

@@ -234,6 +234,37 @@ def test_topk_parity(cmm, ctx, mode):
     assert np.abs(ov - ref_at).max() <= delta
 
 
+TOPK_LARGE = [
+    # (n1, n3, m, b, d, K, mode): at least 64 tiles of 16 rows, so the sampled
+    # threshold and the fused histogram + collect pass run
+    (1500, 1400, 200, 1 << 14, 5, 64, "all"),
+    (1600, 1600, 150, 1 << 14, 3, 2048, "upper"),
+    (1200, 1300, 100, 1024, 1, 50, "all"),      # d = 1: ~1500 equal magnitudes per bucket
+    (1024, 1024, 64, 4096, 1, 1, "upper"),
+]
+
+
+@pytest.mark.parametrize("case", TOPK_LARGE, ids=[f"{c[0]}x{c[1]}_b{c[3]}_d{c[4]}_K{c[5]}_{c[6]}" for c in TOPK_LARGE])
+def test_topk_parity_large_domain(cmm, ctx, case):
+    n1, n3, m, b, d, K, mode = case
+    _say(f"case: top-K large domain {case}")
+    At, B = _rand_problem(n1, m, n3, 1000 + n1 + K)
+    sk = cmm.sketch_product(ctx, _dev(At), _dev(B), b, d, seed=61 + K)
+    c_ref, tabs, _ = _oracle_c(At, B, b, d, 61 + K)
+    oi, oj, ov = sk.topk(K, mode)
+    i, j = O.candidates(mode, n1, n3)
+    vals = O.decode(c_ref, tabs, i, j)
+    delta = 2 * (np.abs(sk.c().astype(np.float32).astype(np.float64) - c_ref).max() + 1e-6 * np.abs(c_ref).max())
+    _check_topk(oi * n3 + oj, ov, vals, i * n3 + j, K, delta)
+    assert np.abs(ov - O.decode(c_ref, tabs, oi, oj)).max() <= delta
+    if mode == "upper":
+        assert np.all(oi < oj)
+    # equal magnitudes come out in increasing linear index
+    mag, lin = np.abs(ov), oi * n3 + oj
+    same = mag[1:] == mag[:-1]
+    assert np.all(lin[1:][same] > lin[:-1][same])
+
+
 def test_topk_per_column_parity(cmm, ctx):
     _say("case: top-K per column")
     At, B = _rand_problem(500, 120, 64, 17)
