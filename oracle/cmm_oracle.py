@@ -308,6 +308,95 @@ def decode_all(c: np.ndarray, tables, n1: int, n3: int, row_block: int = 512) ->
 
 
 # ---------------------------------------------------------------------------
+# Frobenius-norm upper bound (Section 5.2, from the AMS sketch of Section 2.1)
+# ---------------------------------------------------------------------------
+
+# Reading (the paper leaves the source open): the sign polynomials of the
+# bound use the same SplitMix64 stream as the count-sketch hashes, from output
+# 1024 on (the count sketch uses at most z_1..z_504, d <= 63).
+AMS_STREAM_OFFSET = 1024
+
+
+def ams_params(seed: int, d: int) -> np.ndarray:
+    """(d, 2, 4) uint64 coefficients (a0, a1, a2, a3) of the degree-3 sign
+    polynomials of s1 (f = 0) and s2 (f = 1) of every repetition t:
+    a_c = z_{1024 + 8t + 4f + c + 1} mod (2^61 - 1).  Degree-3 polynomials
+    with uniform coefficients form a 4-wise independent family, as Section
+    5.2 asks of s1 and s2.  Pinned by the 4-point sign statistics in the
+    tests."""
+    z = splitmix64(seed, AMS_STREAM_OFFSET + 8 * d)
+    out = np.zeros((d, 2, 4), dtype=np.uint64)
+    for t in range(d):
+        for f in range(2):
+            for c in range(4):
+                out[t, f, c] = z[AMS_STREAM_OFFSET + 8 * t + 4 * f + c] % P61
+    return out
+
+
+def poly_hash(coefs, xs) -> list[int]:
+    """sum_c a_c x^c mod (2^61 - 1), exact integers.  Pinned by hand values
+    at the modulus edges."""
+    cs = [int(a) for a in coefs]
+    return [sum(a * pow(int(x), c, P61) for c, a in enumerate(cs)) % P61 for x in xs]
+
+
+def ams_signs(params: np.ndarray, n1: int, n3: int):
+    """s1 (d, n1) and s2 (d, n3) in {-1, +1}: +1 where the polynomial value is
+    even (as for the count-sketch signs)."""
+    d = params.shape[0]
+    s1 = np.zeros((d, n1), np.int64); s2 = np.zeros((d, n3), np.int64)
+    for t in range(d):
+        s1[t] = [1 - 2 * (g % 2) for g in poly_hash(params[t, 0], range(n1))]
+        s2[t] = [1 - 2 * (g % 2) for g in poly_hash(params[t, 1], range(n3))]
+    return s1, s2
+
+
+def ams_sketch(AB: np.ndarray, s1: np.ndarray, s2: np.ndarray) -> np.ndarray:
+    """X_t = sum over (i,j) of s1_t(i) s2_t(j) (AB)_ij: the AMS sketch of AB
+    with the product sign s(i,j) = s1(i) s2(j) (Section 2.1), one per
+    repetition.  Definition form; pinned against ``ams_sketch_outer``, a hand
+    example and the moments of Section 5.2."""
+    AB = np.asarray(AB, dtype=np.float64)
+    return np.array([float(s1[t].astype(np.float64) @ AB @ s2[t].astype(np.float64))
+                     for t in range(s1.shape[0])])
+
+
+def ams_sketch_outer(A: np.ndarray, B: np.ndarray, s1: np.ndarray, s2: np.ndarray) -> np.ndarray:
+    """The same sketch summed over the outer products a_k b_k of eq. (1): the
+    sketch of an outer product is the product of the two vectors' sketches
+    (Section 2.1), X_t = sum_k (sum_i s1(i) A_ik)(sum_j s2(j) B_kj)."""
+    A = np.asarray(A, dtype=np.float64); B = np.asarray(B, dtype=np.float64)
+    out = np.zeros(s1.shape[0])
+    for t in range(s1.shape[0]):
+        u = s1[t].astype(np.float64) @ A          # one value per k
+        v = B @ s2[t].astype(np.float64)          # one value per k
+        out[t] = float(np.sum(u * v))
+    return out
+
+
+def frobenius_bound(X: np.ndarray) -> float:
+    """32 times the median over repetitions of X_t^2: X^2 is an unbiased
+    estimator of ||AB||_F^2 with variance at most 8 E[X^2]^2, so by
+    Chebyshev it is within a factor 32 with probability 3/4, and the median
+    of d estimators times 32 is an upper bound with high probability
+    (Section 5.2)."""
+    return 32.0 * float(median(np.asarray(X, dtype=np.float64) ** 2, 0))
+
+
+def frobenius(A: np.ndarray, B: np.ndarray, d: int, seed: int, subtract_diag: bool = False):
+    """(X, bound, s1, s2) for AB (with its diagonal zeroed if asked, the Q~ of
+    Section 3.2)."""
+    n1, n3 = A.shape[0], B.shape[1]
+    s1, s2 = ams_signs(ams_params(seed, d), n1, n3)
+    AB = np.asarray(A, dtype=np.float64) @ np.asarray(B, dtype=np.float64)
+    if subtract_diag:
+        AB = AB.copy()
+        np.fill_diagonal(AB, 0.0)
+    X = ams_sketch(AB, s1, s2)
+    return X, frobenius_bound(X), s1, s2
+
+
+# ---------------------------------------------------------------------------
 # a whole product, as the GPU path is asked for it
 # ---------------------------------------------------------------------------
 

@@ -318,3 +318,109 @@ def test_sketch_buckets_matches_definition():
         np.testing.assert_allclose(O.sketch_buckets(A, B, tabs, 32, t, us), full[t, us], atol=1e-12)
         np.testing.assert_allclose(O.sketch_buckets(A, B, tabs, 32, t, us, zero_diagonal=True),
                                    zeroed[t, us], atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Frobenius-norm bound (Section 5.2; AMS sketch of Section 2.1)
+# --------------------------------------------------------------------------
+
+def test_poly_hash_hand_values():
+    P = O.P61
+    assert O.poly_hash([5, 0, 0, 0], [0, 1, 12345]) == [5, 5, 5]
+    assert O.poly_hash([0, 1, 0, 0], [P - 1, P, P + 3]) == [P - 1, 0, 3]
+    # x^3: (p-1)^3 = -1 mod p; 2^21 cubed is 2^63 = 4 * 2^61 = 4 mod p
+    assert O.poly_hash([0, 0, 0, 1], [P - 1, 2, 1 << 21]) == [P - 1, 8, 4]
+    assert O.poly_hash([1, 1, 1, 1], [2]) == [15]
+    assert O.poly_hash([P - 1, P - 1, 0, 0], [1]) == [P - 2]
+
+
+def test_ams_params_stream_and_range():
+    p = O.ams_params(77, 3)
+    z = O.splitmix64(77, 1024 + 24)
+    assert p.shape == (3, 2, 4)
+    assert int(p[2, 1, 3]) == z[1024 + 8 * 2 + 4 * 1 + 3] % O.P61
+    assert all(int(v) < O.P61 for v in p.ravel())
+
+
+def _signs_at(seed, xs):
+    p = O.ams_params(seed, 1)
+    return [1 - 2 * (g % 2) for g in O.poly_hash(p[0, 0], xs)]
+
+
+@pytest.mark.parametrize("xs", [(0, 1, 2, 3), (5, 1000, 77, 1 << 20)])
+def test_ams_signs_four_wise(xs):
+    """Degree-3 polynomial signs are 4-wise independent (Section 5.2 needs
+    it): over many seeds every pattern of the four signs is equally likely,
+    and every product of two, three or four of them averages to 0."""
+    S = 1600
+    pats = np.zeros(16, np.int64)
+    prods = {k: [] for k in [(0, 1), (1, 2), (0, 3), (0, 1, 2), (1, 2, 3), (0, 1, 2, 3)]}
+    for seed in range(S):
+        s = _signs_at(seed, xs)
+        pats[sum((1 if s[q] < 0 else 0) << q for q in range(4))] += 1
+        for k in prods:
+            prods[k].append(np.prod([s[q] for q in k]))
+    chi2 = float(((pats - S / 16) ** 2 / (S / 16)).sum())
+    assert chi2 < 45.0, chi2          # 15 dof; P(chi2 > 45) < 1e-4
+    for k, v in prods.items():
+        assert abs(np.mean(v)) < 4.5 / np.sqrt(S), (k, np.mean(v))
+
+
+def test_ams_sketch_definition_equals_outer_products():
+    g = np.random.default_rng(3)
+    A = g.standard_normal((9, 5)); B = g.standard_normal((5, 7))
+    s1, s2 = O.ams_signs(O.ams_params(11, 4), 9, 7)
+    np.testing.assert_allclose(O.ams_sketch(A @ B, s1, s2), O.ams_sketch_outer(A, B, s1, s2),
+                               rtol=1e-12, atol=1e-12)
+
+
+def test_ams_hand_example():
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "hand_ams.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            rows[k] = [float(x) for x in v]
+    A = np.array(rows["A"])[:, None]; B = np.array(rows["B"])[None, :]
+    s1 = np.array([rows["s1"]], np.int64); s2 = np.array([rows["s2"]], np.int64)
+    assert O.ams_sketch(A @ B, s1, s2)[0] == rows["X"][0]
+    assert O.ams_sketch_outer(A, B, s1, s2)[0] == rows["X"][0]
+    Z = A @ B
+    np.fill_diagonal(Z, 0.0)
+    assert O.ams_sketch(Z, s1, s2)[0] == rows["X_zero_diagonal"][0]
+
+
+def test_ams_moments_section_5_2():
+    """X^2 is unbiased for ||AB||_F^2 with variance at most 8 E[X^2]^2."""
+    g = np.random.default_rng(8)
+    A = g.standard_normal((12, 8)); B = g.standard_normal((8, 10))
+    AB = A @ B
+    F2 = float((AB ** 2).sum())
+    S = 1500
+    x2 = np.array([O.ams_sketch(AB, *O.ams_signs(O.ams_params(seed, 1), 12, 10))[0] ** 2
+                   for seed in range(S)])
+    se = x2.std() / np.sqrt(S)
+    assert abs(x2.mean() - F2) < 4 * se, (x2.mean(), F2, se)
+    assert x2.var() <= 8 * F2 ** 2 * 1.2
+
+
+def test_frobenius_bound_holds_and_is_not_vacuous():
+    """32 * median of d = 9 estimators bounds ||AB||_F^2 from above.
+
+    Chebyshev with Var(X^2) <= 8 E[X^2]^2 controls only the upper tail
+    (P(X^2 > 32 ||AB||_F^2) <= 8/31^2).  Whether 32 * median stays above
+    ||AB||_F^2 depends on the lower tail P(X^2 < ||AB||_F^2 / 32), about 0.17
+    per estimator for this product (near-Gaussian X gives 0.14), so the median
+    of 9 falls short with probability about 1e-2: the bound may fail rarely,
+    and fails for at most a few of 200 seeds."""
+    g = np.random.default_rng(9)
+    A = g.standard_normal((10, 6)); B = g.standard_normal((6, 11))
+    F2 = float(((A @ B) ** 2).sum())
+    ratios, fails, over = [], 0, 0
+    for seed in range(200):
+        X, bound, _, _ = O.frobenius(A, B, 9, 5000 + seed)
+        fails += bound < F2
+        over += int(np.sum(X ** 2 > 32 * F2))
+        ratios.append(bound / F2)
+    assert fails <= 8, fails                   # expected about 2
+    assert over <= 0.02 * 200 * 9, over        # Chebyshev: rate <= 8/961
+    assert np.median(ratios) < 64.0
