@@ -200,6 +200,36 @@ def run_batched(ctx, steps, warmup, with_oracle=True):
     return out
 
 
+def run_frobenius(ctx, w, steps):
+    """The Frobenius-norm bound of Section 5.2 on the same operands and d:
+    sign tables, two sign-weighted row-sum passes (one read of A and of B),
+    the per-repetition dot products; HIP-event time per call, input GB/s."""
+    import numpy as np
+    import torch
+    import paper_1108_1320_amd as cmm
+    esz = {"f32": 4, "bf16": 2, "fp8": 1}[w.dtype]
+    At = torch.from_numpy(np.ascontiguousarray(w.At_store)).cuda()
+    Bd = At.clone() if w.same_operand else torch.from_numpy(np.ascontiguousarray(w.B_store)).cuda()
+    sA = torch.from_numpy(w.scaleA).cuda() if w.scaleA is not None else None
+    sB = torch.from_numpy(w.scaleB).cuda() if w.scaleB is not None else None
+
+    def call():
+        return cmm.frobenius_bound(ctx, At, Bd, w.d, seed=w.seed, dtype=w.dtype, scaleA=sA, scaleB=sB,
+                                   subtract_diag=w.subtract_diag, n1=w.n1, n3=w.n3, m=w.m)
+    call()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    for _ in range(steps):
+        X, bound = call()
+    ms, n = ctx.profile_read("frobenius")
+    ctx.profile(False)
+    avg = ms / max(n, 1)
+    nbytes = (w.n1 * w.m + w.m * w.n3) * esz
+    return {"ms": round(avg, 4), "input_GBps": round(nbytes / (avg * 1e-3) / 1e9, 1),
+            "hbm_frac": round(nbytes / (avg * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "bound": bound, "median_X2": bound / 32.0, "d": w.d}
+
+
 def traffic_record(w):
     """HBM bytes per fft_mac launch from the committed rocprofv3 counter
     summary, if it was taken on this workload and the kernel source has not
@@ -322,10 +352,14 @@ def main():
             "avg_ms": round(cs_avg_ms, 4),
         },
     }
+    out["frobenius_bound"] = run_frobenius(ctx, w, args.steps)
     c_ref = None
     if not args.no_cpu:
         out["cpu_baseline"], out["parity"], c_ref = cpu_baseline(w, c_gpu, oi, oj, ov, input_bytes)
         out["parity"]["planted_recall"] = planted_recall(w, oi, oj)
+        fb = out["frobenius_bound"]
+        fb["bound_over_true"] = round(fb["bound"] / out["parity"]["frobenius_norm_sq"], 3)
+        fb["median_X2_over_true"] = round(fb["median_X2"] / out["parity"]["frobenius_norm_sq"], 4)
     if not args.no_compare and w.dtype == "f32" and w.mode != "column":
         out["bf16_same_workload"] = compare_bf16(ctx, args, w, c_ref, oi, oj, value)
     if not args.no_batched:
@@ -405,9 +439,14 @@ def cpu_baseline(w, c_gpu, oi, oj, ov, input_bytes):
     est_err = None
     if w.mode != "column":
         est_err = float(np.abs(ov - O.decode(c_ref, tabs, oi, oj)).max())
+    AB0 = AB.copy()
+    if w.subtract_diag:
+        np.fill_diagonal(AB0, 0.0)
+    fro2 = float((AB0 ** 2).sum())
     base = {"value": round(input_bytes / secs / 1e9, 4), "unit": "GB/s", "cores": cores,
             "kind": "oracle", "sample": sample, "seconds": round(secs, 2)}
-    parity = {"max_rel_l2_c": rel, "max_abs_err_topk_values": est_err, "tolerance": 1e-5}
+    parity = {"max_rel_l2_c": rel, "max_abs_err_topk_values": est_err, "tolerance": 1e-5,
+              "frobenius_norm_sq": fro2}
     return base, parity, c_ref
 
 

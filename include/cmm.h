@@ -112,7 +112,8 @@ const char* cmm_last_error(const cmm_ctx* ctx);
 /* Kernel timing: while enabled, the library records a pair of HIP events on
  * the context stream around every launch of the named kernels and sums
  * their durations.  `name` is one of "hash", "layout", "countsketch",
- * "fft_mac", "ifft", "decode", or "batch" (a whole graph replay of
+ * "fft_mac", "ifft", "decode", "frobenius" (cmm_frobenius_bound), or
+ * "batch" (a whole graph replay of
  * cmm_batch_run; the kernels inside a graph are not timed one by one).
  * Reading waits for the stream. */
 int cmm_ctx_profile(cmm_ctx* ctx, int enable);
@@ -237,6 +238,30 @@ int cmm_tuning_set(cmm_ctx* ctx, int64_t n1, int64_t m, int64_t n3, int64_t b, i
                    int32_t dtype, const int32_t* tuning);
 int cmm_tuning_save(const cmm_ctx* ctx, const char* path);
 int cmm_tuning_load(cmm_ctx* ctx, const char* path);
+
+/* ---- Frobenius-norm bound (Section 5.2) -------------------------------- */
+
+/* Upper bound on ||AB||_F^2 from AMS sketches (Section 2.1): for every
+ * repetition t, X_t = sum_ij s1_t(i) s2_t(j) (AB)_ij, computed without AB as
+ * sum_k (sum_i s1_t(i) A_ik)(sum_j s2_t(j) B_kj).  s1_t and s2_t are 4-wise
+ * independent: the parity of a degree-3 polynomial (a0 + a1 x + a2 x^2 +
+ * a3 x^3) mod (2^61 - 1), s = +1 if even, with a_c = z mod (2^61 - 1) for
+ * z = output 1024 + 8t + 4f + c + 1 of the seed's SplitMix64 stream (f = 0
+ * for s1, 1 for s2).  X_t^2 is unbiased for ||AB||_F^2 with variance at most
+ * 8 (||AB||_F^2)^2; *bound = 32 * median_t X_t^2 (Section 5.2).  Operands,
+ * dtype and scales as in cmm_sketch_product_ex; flags: CMM_SUBTRACT_DIAG
+ * (the bound for AB with its diagonal zeroed, n1 == n3) and CMM_ASYNC (then
+ * X and bound must be NULL).  X (host, d values) and bound (host) may be
+ * NULL.  Sums are float64.  1 <= d <= 63. */
+int cmm_frobenius_bound(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                        int64_t n1, int64_t m, int64_t n3, int32_t dtype, const float* scaleA,
+                        const float* scaleB, int32_t d, uint64_t seed, uint32_t flags, double* X,
+                        double* bound);
+
+/* Host copies of the sign tables of cmm_frobenius_bound (s1[d*n1],
+ * s2[d*n3] in {-1,+1}; either may be NULL), for the bit-exact check. */
+int cmm_frobenius_signs(cmm_ctx* ctx, int64_t n1, int64_t n3, int32_t d, uint64_t seed,
+                        int8_t* s1, int8_t* s2);
 
 /* ---- decoding (DECOMPRESS, Figure 1) ---------------------------------- */
 

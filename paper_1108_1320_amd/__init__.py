@@ -79,6 +79,9 @@ _SIGS = {
     "cmm_tuning_set": (C.c_int, [_P, _I64, _I64, _I64, _I64, _I32, _I32, _I32P]),
     "cmm_tuning_save": (C.c_int, [_P, C.c_char_p]),
     "cmm_tuning_load": (C.c_int, [_P, C.c_char_p]),
+    "cmm_frobenius_bound": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P, _I32,
+                                      _U64, _U32, _P, C.POINTER(C.c_double)]),
+    "cmm_frobenius_signs": (C.c_int, [_P, _I64, _I64, _I32, _U64, _P, _P]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -313,6 +316,23 @@ def cmm_tuning_load(ctx, path: str):
     _check(load().cmm_tuning_load(ctx, path.encode()), "cmm_tuning_load", ctx)
 
 
+def cmm_frobenius_bound(ctx, A, lda, B, ldb, n1, m, n3, dtype, scaleA, scaleB, d, seed, flags=0):
+    """Returns (X[d] float64, 32 * median X^2)."""
+    X = np.empty(d, np.float64); bound = C.c_double()
+    _check(load().cmm_frobenius_bound(ctx, _ptr(A), lda, _ptr(B), ldb, n1, m, n3, dtype,
+                                      _ptr(scaleA), _ptr(scaleB), d, seed, flags,
+                                      X.ctypes.data_as(_P), C.byref(bound)),
+           "cmm_frobenius_bound", ctx)
+    return X, bound.value
+
+
+def cmm_frobenius_signs(ctx, n1, n3, d, seed):
+    s1 = np.empty((d, n1), np.int8); s2 = np.empty((d, n3), np.int8)
+    _check(load().cmm_frobenius_signs(ctx, n1, n3, d, seed, s1.ctypes.data_as(_P),
+                                      s2.ctypes.data_as(_P)), "cmm_frobenius_signs", ctx)
+    return s1, s2
+
+
 # ------------------------------------------------------------- object layer
 
 class Context:
@@ -471,3 +491,16 @@ class Batch:
 def sketch_product_batched(ctx: Context, probs) -> list:
     """Every product of `probs` in one graph launch; returns owned Sketches."""
     return [Sketch(h, ctx) for h in cmm_sketch_product_batched(ctx.handle, probs)]
+
+
+def frobenius_bound(ctx: Context, At, B, d: int, seed: int = 0, dtype: str = "f32", scaleA=None,
+                    scaleB=None, subtract_diag: bool = False, n1: int | None = None,
+                    n3: int | None = None, m: int | None = None):
+    """(X[d], bound) for the k-major device arrays At (m x lda) and B (m x ldb):
+    X_t the AMS sketches of AB, bound = 32 * median X_t^2 >= ||AB||_F^2 whp."""
+    m_ = m if m is not None else At.shape[0]
+    n1_ = n1 if n1 is not None else At.shape[1]
+    n3_ = n3 if n3 is not None else B.shape[1]
+    return cmm_frobenius_bound(ctx.handle, At, At.stride(0), B, B.stride(0), n1_, m_, n3_,
+                               DTYPES[dtype], scaleA, scaleB, d, seed,
+                               CMM_SUBTRACT_DIAG if subtract_diag else 0)

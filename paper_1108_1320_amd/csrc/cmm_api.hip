@@ -169,6 +169,17 @@ void params_from_seed(uint64_t seed, int d, std::vector<uint64_t>& out) {
     }
 }
 
+// Coefficients (a0..a3) of the degree-3 sign polynomials of the Frobenius
+// bound: [t][f][c] = z_{1024 + 8t + 4f + c + 1} mod p, f = 0 for s1, 1 for s2.
+void ams_params_from_seed(uint64_t seed, int d, std::vector<uint64_t>& out) {
+  out.resize((size_t)d * 8);
+  for (int t = 0; t < d; ++t)
+    for (int f = 0; f < 2; ++f)
+      for (int c = 0; c < 4; ++c)
+        out[(size_t)t * 8 + f * 4 + c] =
+            splitmix64_at(seed, (uint64_t)(1024 + 8 * t + 4 * f + c + 1)) % CMM_P61;
+}
+
 int ilog2(int64_t v) { int l = 0; while ((int64_t(1) << l) < v) ++l; return l; }
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -1370,6 +1381,99 @@ int cmm_tuning_load(cmm_ctx* ctx, const char* path) {
   if (!valid_ctx(ctx)) return CMM_EINVAL;
   if (!path) return fail(ctx, CMM_EINVAL, "path is NULL");
   return load_tuning(ctx, path, false);
+}
+
+int cmm_frobenius_signs(cmm_ctx* ctx, int64_t n1, int64_t n3, int32_t d, uint64_t seed,
+                        int8_t* s1, int8_t* s2) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  if (n1 <= 0 || n3 <= 0 || n1 > (1 << 29) || n3 > (1 << 29)) return fail(ctx, CMM_EINVAL, "n1, n3 out of range");
+  if (d < 1 || d > 63) return fail(ctx, CMM_EINVAL, "d must be in [1, 63]");
+  CMM_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  std::vector<uint64_t> pr;
+  ams_params_from_seed(seed, d, pr);
+  Work w(ctx);
+  uint64_t* pdev = w.get<uint64_t>(pr.size());
+  uint64_t* m1 = w.get<uint64_t>((size_t)n1);
+  uint64_t* m2 = w.get<uint64_t>((size_t)n3);
+  if (!pdev || !m1 || !m2) return fail(ctx, CMM_ENOMEM, "workspace allocation failed");
+  CMM_HIP(ctx, hipMemcpyAsync(pdev, pr.data(), sizeof(uint64_t) * pr.size(), hipMemcpyHostToDevice, s));
+  CMM_HIP(ctx, cmm::launch_ams_signs(pdev, d, 0, (int)n1, m1, s));
+  CMM_HIP(ctx, cmm::launch_ams_signs(pdev, d, 1, (int)n3, m2, s));
+  std::vector<uint64_t> h1((size_t)n1), h2((size_t)n3);
+  CMM_HIP(ctx, hipMemcpyAsync(h1.data(), m1, sizeof(uint64_t) * n1, hipMemcpyDeviceToHost, s));
+  CMM_HIP(ctx, hipMemcpyAsync(h2.data(), m2, sizeof(uint64_t) * n3, hipMemcpyDeviceToHost, s));
+  CMM_HIP(ctx, hipStreamSynchronize(s));
+  for (int t = 0; t < d; ++t) {
+    if (s1) for (int64_t x = 0; x < n1; ++x) s1[(int64_t)t * n1 + x] = ((h1[x] >> t) & 1) ? -1 : 1;
+    if (s2) for (int64_t x = 0; x < n3; ++x) s2[(int64_t)t * n3 + x] = ((h2[x] >> t) & 1) ? -1 : 1;
+  }
+  return CMM_OK;
+}
+
+int cmm_frobenius_bound(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                        int64_t n1, int64_t m, int64_t n3, int32_t dtype, const float* scaleA,
+                        const float* scaleB, int32_t d, uint64_t seed, uint32_t flags, double* X,
+                        double* bound) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  int rc = check_operands(ctx, A, lda, B, ldb, n1, m, n3, dtype, 16, d);
+  if (rc) return rc;
+  if (flags & ~(CMM_SUBTRACT_DIAG | CMM_ASYNC)) return fail(ctx, CMM_EINVAL, "unknown flag");
+  if ((flags & CMM_ASYNC) && (X || bound)) return fail(ctx, CMM_EINVAL, "CMM_ASYNC returns no values");
+  if ((flags & CMM_SUBTRACT_DIAG) && n1 != n3) return fail(ctx, CMM_EINVAL, "CMM_SUBTRACT_DIAG needs n1 == n3");
+  if (dtype != CMM_FP8_E4M3 && (scaleA || scaleB))
+    return fail(ctx, CMM_EINVAL, "scales are only taken with CMM_FP8_E4M3");
+  CMM_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  std::vector<uint64_t> pr;
+  ams_params_from_seed(seed, d, pr);
+  Work w(ctx);
+  uint64_t* pdev = w.get<uint64_t>(pr.size());
+  uint64_t* m1 = w.get<uint64_t>((size_t)n1);
+  uint64_t* m2 = w.get<uint64_t>((size_t)n3);
+  double* u = w.get<double>((size_t)d * m);
+  double* v = w.get<double>((size_t)d * m);
+  double* Xd = w.get<double>((size_t)d);
+  if (!pdev || !m1 || !m2 || !u || !v || !Xd) return fail(ctx, CMM_ENOMEM, "workspace allocation failed");
+  double* diag = nullptr;
+  double* partial = nullptr;
+  int kch = 1;
+  if (flags & CMM_SUBTRACT_DIAG) {
+    const int n = (int)n1;
+    kch = (int)std::max<int64_t>(1, std::min<int64_t>(m, 1 + 4096 / ((n + 255) / 256)));
+    diag = w.get<double>((size_t)n);
+    partial = w.get<double>((size_t)kch * n);
+    if (!diag || !partial) return fail(ctx, CMM_ENOMEM, "workspace allocation failed");
+  }
+  CMM_HIP(ctx, hipMemcpyAsync(pdev, pr.data(), sizeof(uint64_t) * pr.size(), hipMemcpyHostToDevice, s));
+  {
+    Scope sc_(ctx, "frobenius");
+    CMM_HIP(ctx, cmm::launch_ams_signs(pdev, d, 0, (int)n1, m1, s));
+    CMM_HIP(ctx, cmm::launch_ams_signs(pdev, d, 1, (int)n3, m2, s));
+    CMM_HIP(ctx, cmm::launch_ams_rows(dtype, A, lda, scaleA, (int)n1, (int)m, d, m1, u, s));
+    CMM_HIP(ctx, cmm::launch_ams_rows(dtype, B, ldb, scaleB, (int)n3, (int)m, d, m2, v, s));
+    if (diag) {
+      cmm::SideDesc sa, sb;
+      sa.X = A; sa.ld = lda; sa.scale = scaleA; sa.n = (int)n1;
+      sb.X = B; sb.ld = ldb; sb.scale = scaleB; sb.n = (int)n3;
+      CMM_HIP(ctx, cmm::launch_diag(dtype, sa, sb, (int)m, (int)n1, partial, kch, diag, s));
+    }
+    CMM_HIP(ctx, cmm::launch_ams_final(u, v, (int)m, d, m1, m2, diag, (int)n1, Xd, s));
+  }
+  if (flags & CMM_ASYNC) return CMM_OK;
+  std::vector<double> xh((size_t)d);
+  CMM_HIP(ctx, hipMemcpyAsync(xh.data(), Xd, sizeof(double) * d, hipMemcpyDeviceToHost, s));
+  CMM_HIP(ctx, hipStreamSynchronize(s));
+  if (X) std::copy(xh.begin(), xh.end(), X);
+  if (bound) {
+    std::vector<double> sq(xh.size());
+    for (size_t t = 0; t < xh.size(); ++t) sq[t] = xh[t] * xh[t];
+    std::sort(sq.begin(), sq.end());
+    const size_t h = sq.size() / 2;
+    const double med = (sq.size() & 1) ? sq[h] : 0.5 * (sq[h - 1] + sq[h]);
+    *bound = 32.0 * med;
+  }
+  return CMM_OK;
 }
 
 }  // extern "C"

@@ -37,6 +37,41 @@ namespace cmm {
 // with bits 4..7 (a bijection on [0, C)).
 __host__ __device__ __forceinline__ int fft_swizzle(int i) { return i ^ ((i >> 4) & 15); }
 
+// (a x + c) mod (2^61 - 1) for a, c < 2^61 - 1 and x < 2^32, exact: the
+// 93-bit product is folded with 2^61 = 1 (mod p).  One step of Horner's rule
+// for longer polynomials.
+__device__ __forceinline__ uint64_t cw_hash61(uint64_t a, uint64_t x, uint64_t c) {
+  uint64_t lo = a * x;
+  uint64_t hi = __umul64hi(a, x);           // < 2^29 since a < 2^61, x < 2^32
+  uint64_t s = lo + c;
+  hi += (s < lo) ? 1ull : 0ull;
+  // v = hi 2^64 + s and 2^64 = 8 (mod p): fold both words into 61-bit digits
+  uint64_t r = (s & CMM_P61) + (s >> 61) + (hi << 3);
+  r = (r & CMM_P61) + (r >> 61);
+  if (r >= CMM_P61) r -= CMM_P61;
+  return r;
+}
+
+// OCP e4m3fn code (low 8 bits of v) to float32: bias 7, no infinities,
+// S.1111.111 is NaN, subnormals m * 2^-9.
+__device__ __forceinline__ float e4m3fn_to_f32(uint32_t v) {
+  uint32_t sign = (v & 0x80u) << 24;
+  uint32_t e = (v >> 3) & 0xFu, mnt = v & 7u;
+  float mag;
+  if (e == 0) mag = (float)mnt * 0x1p-9f;
+  else if (e == 15 && mnt == 7) mag = __uint_as_float(0x7FC00000u);
+  else mag = __uint_as_float(((e + 120u) << 23) | (mnt << 20));
+  return __uint_as_float(__float_as_uint(mag) | sign);
+}
+
+// Element `off` of a stored operand as float32 (0: f32, 1: bf16 bits,
+// 2: e4m3fn code; the fp8 column scale is applied by the caller).
+template <int DT> __device__ __forceinline__ float load_deq(const void* X, int64_t off) {
+  if constexpr (DT == 0) return ((const float*)X)[off];
+  else if constexpr (DT == 1) return __uint_as_float((uint32_t)((const uint16_t*)X)[off] << 16);
+  else return e4m3fn_to_f32(((const uint8_t*)X)[off]);
+}
+
 // Fold entry of bucket u for an FFT row of length C = 1 << log2c, as two
 // byte offsets of 8-byte LDS elements: bits 0..15 hold 8 * (swizzled slot of
 // u mod C) (C <= 8192), bits 16..31 hold 8 * (weight index u >> log2(C/16)),
@@ -128,6 +163,13 @@ hipError_t launch_sub_diag(const Geometry& g, const int32_t* hs1, const int32_t*
                            int n3, const double* diag, int len, double* c64, hipStream_t s);
 hipError_t launch_to_f32(const double* c64, float* c32, int64_t count, hipStream_t s);
 hipError_t launch_add_f64(double* dst, const double* src, int64_t count, hipStream_t s);
+hipError_t launch_ams_signs(const uint64_t* params, int d, int side, int n, uint64_t* mask,
+                            hipStream_t s);
+hipError_t launch_ams_rows(int dtype, const void* X, int64_t ld, const float* scale, int n, int m,
+                           int d, const uint64_t* mask, double* out, hipStream_t s);
+hipError_t launch_ams_final(const double* u, const double* v, int m, int d, const uint64_t* mask1,
+                            const uint64_t* mask2, const double* diag, int ndiag, double* X,
+                            hipStream_t s);
 hipError_t launch_fill_random(void* X, int64_t count, int dtype, uint64_t seed, hipStream_t s);
 
 struct DecodeDesc {

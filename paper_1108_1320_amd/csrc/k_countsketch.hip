@@ -17,15 +17,6 @@
 
 namespace cmm {
 
-__device__ __forceinline__ float e4m3fn_to_f32(uint32_t v) {
-  uint32_t sign = (v & 0x80u) << 24;
-  uint32_t e = (v >> 3) & 0xFu, mnt = v & 7u;
-  float mag;
-  if (e == 0) mag = (float)mnt * 0x1p-9f;
-  else if (e == 15 && mnt == 7) mag = __uint_as_float(0x7FC00000u);
-  else mag = __uint_as_float(((e + 120u) << 23) | (mnt << 20));
-  return __uint_as_float(__float_as_uint(mag) | sign);
-}
 
 template <int DT> struct Elem;
 template <> struct Elem<0> {      // f32

@@ -9,17 +9,6 @@
 
 namespace cmm {
 
-__device__ __forceinline__ uint64_t cw_hash61(uint64_t a, uint64_t x, uint64_t c) {
-  uint64_t lo = a * x;
-  uint64_t hi = __umul64hi(a, x);           // < 2^29 since a < 2^61, x < 2^32
-  uint64_t s = lo + c;
-  hi += (s < lo) ? 1ull : 0ull;
-  // v = hi 2^64 + s and 2^64 = 8 (mod p): fold both words into 61-bit digits
-  uint64_t r = (s & CMM_P61) + (s >> 61) + (hi << 3);
-  r = (r & CMM_P61) + (r >> 61);
-  if (r >= CMM_P61) r -= CMM_P61;
-  return r;
-}
 
 __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t v) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;

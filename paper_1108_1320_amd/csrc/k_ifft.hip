@@ -130,23 +130,6 @@ hipError_t launch_ifft(const Geometry& g, const float2* Ppart, double2* work0, d
 
 // ---------------------------------------------------------------- diagonal
 
-template <int DT> __device__ __forceinline__ float load_deq(const void* X, int64_t off);
-template <> __device__ __forceinline__ float load_deq<0>(const void* X, int64_t off) {
-  return ((const float*)X)[off];
-}
-template <> __device__ __forceinline__ float load_deq<1>(const void* X, int64_t off) {
-  return __uint_as_float((uint32_t)((const uint16_t*)X)[off] << 16);
-}
-template <> __device__ __forceinline__ float load_deq<2>(const void* X, int64_t off) {
-  uint32_t v = ((const uint8_t*)X)[off];
-  uint32_t sign = (v & 0x80u) << 24;
-  uint32_t e = (v >> 3) & 0xFu, mnt = v & 7u;
-  float mag;
-  if (e == 0) mag = (float)mnt * 0x1p-9f;
-  else if (e == 15 && mnt == 7) mag = __uint_as_float(0x7FC00000u);
-  else mag = __uint_as_float(((e + 120u) << 23) | (mnt << 20));
-  return __uint_as_float(__float_as_uint(mag) | sign);
-}
 
 // partial[kc][i] = sum over k in chunk kc of A[i,k] B[k,i] (float64)
 template <int DT>
