@@ -397,6 +397,87 @@ def frobenius(A: np.ndarray, B: np.ndarray, d: int, seed: int, subtract_diag: bo
 
 
 # ---------------------------------------------------------------------------
+# sublinear extraction of significant entries (Section 4, Figure 3)
+# ---------------------------------------------------------------------------
+
+# Reading: the paper's expander code is not given.  The code used is the
+# complement code E(x) = bits(x) || not bits(x) over L = max(1, ceil(log2 n))
+# bits, l = 2L: every codeword has weight L, DECODE accepts a string only if
+# each pair (bit q, bit q + L) is (1, 0) or (0, 1) and fails otherwise (an
+# empty bucket, all bits 0, never decodes), and the d/2 vote over the
+# repetitions removes wrongly decoded positions.
+
+
+def code_bits(n: int) -> int:
+    """L = number of information bits for indices 0..n-1."""
+    return max(1, int(np.ceil(np.log2(n)))) if n > 1 else 1
+
+
+def code_encode(x: int, L: int) -> list[int]:
+    """E(x) = bits(x) (least significant first) followed by their complements."""
+    bits = [(x >> q) & 1 for q in range(L)]
+    return bits + [1 - v for v in bits]
+
+
+def code_decode(s, L: int):
+    """x from a bit string of length 2L, or None if some pair is not (1,0)/(0,1)."""
+    x = 0
+    for q in range(L):
+        a, c = int(s[q]), int(s[q + L])
+        if a == c:
+            return None
+        x |= a << q
+    return x
+
+
+def masked_sketches(A: np.ndarray, B: np.ndarray, tables, b: int, subtract_diag: bool = False):
+    """Count sketches, with the same hash functions, of the submatrix products
+    of eq. (3): (I_{E_r} A) B for the 2 L1 bits r of the row code and
+    A (B I_{E_r}) for the 2 L3 bits of the column code.  Returns
+    (c_rows (2L1, d, b), c_cols (2L3, d, b))."""
+    A = np.asarray(A, dtype=np.float64); B = np.asarray(B, dtype=np.float64)
+    n1, n3 = A.shape[0], B.shape[1]
+    L1, L3 = code_bits(n1), code_bits(n3)
+    E1 = np.array([code_encode(i, L1) for i in range(n1)])   # (n1, 2 L1)
+    E3 = np.array([code_encode(j, L3) for j in range(n3)])   # (n3, 2 L3)
+    rows, cols = [], []
+    for r in range(2 * L1):
+        P = (A * E1[:, r][:, None]) @ B
+        if subtract_diag:
+            np.fill_diagonal(P, 0.0)
+        rows.append(bin_product(P, tables, b))
+    for r in range(2 * L3):
+        P = A @ (B * E3[:, r][None, :])
+        if subtract_diag:
+            np.fill_diagonal(P, 0.0)
+        cols.append(bin_product(P, tables, b))
+    return np.array(rows), np.array(cols)
+
+
+def find_significant(c_rows: np.ndarray, c_cols: np.ndarray, n1: int, n3: int, delta: float):
+    """FINDSIGNIFICANTENTRIES (Figure 3): for every repetition t and bucket k,
+    the bit string s_r = [|p^(t,r)[k]| > delta/2] over the row-code sketches
+    and then the column-code sketches is decoded into (i, j) and inserted
+    into a multiset; positions inserted fewer than d/2 times are deleted.
+    Returns the sorted linear indices i*n3 + j of the kept positions and the
+    multiset counts."""
+    L1, L3 = code_bits(n1), code_bits(n3)
+    d, b = c_rows.shape[1], c_rows.shape[2]
+    counts: dict[int, int] = {}
+    for t in range(d):
+        for k in range(b):
+            s1 = [abs(c_rows[r, t, k]) > delta / 2 for r in range(2 * L1)]
+            s3 = [abs(c_cols[r, t, k]) > delta / 2 for r in range(2 * L3)]
+            i, j = code_decode(s1, L1), code_decode(s3, L3)
+            if i is None or j is None or i >= n1 or j >= n3:
+                continue
+            key = i * n3 + j
+            counts[key] = counts.get(key, 0) + 1
+    kept = sorted(k for k, v in counts.items() if 2 * v >= d)
+    return np.array(kept, dtype=np.int64), counts
+
+
+# ---------------------------------------------------------------------------
 # a whole product, as the GPU path is asked for it
 # ---------------------------------------------------------------------------
 

@@ -424,3 +424,74 @@ def test_frobenius_bound_holds_and_is_not_vacuous():
     assert fails <= 8, fails                   # expected about 2
     assert over <= 0.02 * 200 * 9, over        # Chebyshev: rate <= 8/961
     assert np.median(ratios) < 64.0
+
+
+# --------------------------------------------------------------------------
+# sublinear extraction (Section 4, Figure 3) with the complement code
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 3, 1000, 4096])
+def test_code_roundtrip_and_detection(n):
+    L = O.code_bits(n)
+    assert (1 << L) >= n
+    for x in range(0, n, max(1, n // 300)):
+        e = O.code_encode(x, L)
+        assert len(e) == 2 * L and sum(e) == L
+        assert O.code_decode(e, L) == x
+        for q in range(2 * L):                 # any single flipped bit is detected
+            f = list(e); f[q] ^= 1
+            assert O.code_decode(f, L) is None
+    assert O.code_decode([0] * (2 * L), L) is None   # empty bucket
+    assert O.code_decode([1] * (2 * L), L) is None   # two colliding entries
+
+
+def _sparse_product(n1, m, n3, nnz, seed, small=0):
+    """A (n1 x m, full row rank) and B = pinv(A) S, so AB = S exactly up to
+    rounding: nnz entries of magnitude in [1, 2] (and `small` of 0.01)."""
+    g = np.random.default_rng(seed)
+    A = g.standard_normal((n1, m))
+    S = np.zeros((n1, n3))
+    pos = g.choice(n1 * n3, nnz + small, replace=False)
+    S.flat[pos[:nnz]] = g.choice([-1.0, 1.0], nnz) * g.uniform(1.0, 2.0, nnz)
+    S.flat[pos[nnz:]] = 0.01
+    B = np.linalg.pinv(A) @ S
+    return A, B, np.sort(pos[:nnz])
+
+
+@pytest.mark.parametrize("case", [(64, 64, 64, 12, 256, 7), (40, 90, 70, 20, 512, 9),
+                                  (100, 120, 30, 8, 128, 5)])
+def test_find_significant_recovers_sparse_product(case):
+    """Theorem 7 / Corollary 8: a product with few non-zeros (far fewer than
+    b) is returned exactly: every non-zero position and nothing else."""
+    n1, m, n3, nnz, b, d = case
+    A, B, support = _sparse_product(n1, m, n3, nnz, n1 + n3)
+    tabs = O.hash_tables(O.hash_params(17, d), n1, n3, b)
+    cr, cc = O.masked_sketches(A, B, tabs, b)
+    kept, _ = O.find_significant(cr, cc, n1, n3, 0.5)
+    np.testing.assert_array_equal(kept, support)
+
+
+def test_find_significant_omits_entries_below_delta():
+    """Entries well below Delta are not reported (Theorem 7 may omit them);
+    entries well above it are."""
+    A, B, support = _sparse_product(60, 80, 60, 10, 3, small=25)
+    tabs = O.hash_tables(O.hash_params(23, 7), 60, 60, 512)
+    cr, cc = O.masked_sketches(A, B, tabs, 512)
+    kept, _ = O.find_significant(cr, cc, 60, 60, 0.5)
+    np.testing.assert_array_equal(kept, support)
+
+
+def test_masked_sketch_definition():
+    """Masked sketch r is the sketch of the product with the rows (columns)
+    whose code bit r is 0 removed: with every bit pair complementary, the
+    two sketches of a pair add up to the sketch of the whole product."""
+    g = np.random.default_rng(2)
+    A = g.standard_normal((20, 9)); B = g.standard_normal((9, 13))
+    tabs = O.hash_tables(O.hash_params(4, 3), 20, 13, 64)
+    cr, cc = O.masked_sketches(A, B, tabs, 64)
+    whole = O.bin_product(A @ B, tabs, 64)
+    L1, L3 = O.code_bits(20), O.code_bits(13)
+    for q in range(L1):
+        np.testing.assert_allclose(cr[q] + cr[q + L1], whole, atol=1e-12)
+    for q in range(L3):
+        np.testing.assert_allclose(cc[q] + cc[q + L3], whole, atol=1e-12)
