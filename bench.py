@@ -62,6 +62,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-compare", action="store_true", help="skip the bf16 run of the same workload")
     p.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
+    p.add_argument("--no-extract", action="store_true", help="skip the sublinear-extraction measurement")
     p.add_argument("--no-autotune", action="store_true",
                    help="use the built-in geometry instead of tuning the size class first")
     p.add_argument("--copy-calibration", action="store_true",
@@ -230,6 +231,41 @@ def run_frobenius(ctx, w, steps):
             "bound": bound, "median_X2": bound / 32.0, "d": w.d}
 
 
+def run_extract(ctx, w, median_x2):
+    """FINDSIGNIFICANTENTRIES (Section 4) on the same operands: delta = 3 x
+    the Frobenius estimate sqrt(median X^2) / sqrt(b); time of one call
+    (1 + 2(L1 + L3) sketch products, decode and vote), positions returned
+    and the planted pairs among them."""
+    import numpy as np
+    import torch
+    import paper_1108_1320_amd as cmm
+    At = torch.from_numpy(np.ascontiguousarray(w.At_store)).cuda()
+    Bd = At.clone() if w.same_operand else torch.from_numpy(np.ascontiguousarray(w.B_store)).cuda()
+    sA = torch.from_numpy(w.scaleA).cuda() if w.scaleA is not None else None
+    sB = torch.from_numpy(w.scaleB).cuda() if w.scaleB is not None else None
+    delta = 3.0 * float(np.sqrt(max(median_x2, 0.0) / w.b))
+
+    def call():
+        return cmm.find_significant(ctx, At, Bd, w.b, w.d, delta, seed=w.seed, dtype=w.dtype,
+                                    scaleA=sA, scaleB=sB, subtract_diag=w.subtract_diag,
+                                    n1=w.n1, n3=w.n3, m=w.m)
+    call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gi, gj, total = call()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    L1 = max(1, int(np.ceil(np.log2(w.n1)))); L3 = max(1, int(np.ceil(np.log2(w.n3))))
+    res = {"ms": round(ms, 2), "delta": round(delta, 3), "sketch_products": 1 + 2 * (L1 + L3),
+           "returned": int(total)}
+    if w.planted is not None and w.mode == "upper":
+        got = {(int(a), int(c)) for a, c in zip(gi, gj)}
+        want = {(int(min(p, q)), int(max(p, q))) for p, q in w.planted}
+        res["planted_found"] = len({(min(a, c), max(a, c)) for a, c in got} & want)
+        res["planted"] = len(want)
+    return res
+
+
 def traffic_record(w):
     """HBM bytes per fft_mac launch from the committed rocprofv3 counter
     summary, if it was taken on this workload and the kernel source has not
@@ -353,6 +389,8 @@ def main():
         },
     }
     out["frobenius_bound"] = run_frobenius(ctx, w, args.steps)
+    if not args.no_extract and w.mode != "column":
+        out["find_significant"] = run_extract(ctx, w, out["frobenius_bound"]["median_X2"])
     c_ref = None
     if not args.no_cpu:
         out["cpu_baseline"], out["parity"], c_ref = cpu_baseline(w, c_gpu, oi, oj, ov, input_bytes)

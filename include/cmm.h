@@ -112,7 +112,8 @@ const char* cmm_last_error(const cmm_ctx* ctx);
 /* Kernel timing: while enabled, the library records a pair of HIP events on
  * the context stream around every launch of the named kernels and sums
  * their durations.  `name` is one of "hash", "layout", "countsketch",
- * "fft_mac", "ifft", "decode", "frobenius" (cmm_frobenius_bound), or
+ * "fft_mac", "ifft", "decode", "frobenius" (cmm_frobenius_bound), "extract"
+ * (the masked sketches, decoding and vote of cmm_find_significant), or
  * "batch" (a whole graph replay of
  * cmm_batch_run; the kernels inside a graph are not timed one by one).
  * Reading waits for the stream. */
@@ -262,6 +263,32 @@ int cmm_frobenius_bound(cmm_ctx* ctx, const void* A, int64_t lda, const void* B,
  * s2[d*n3] in {-1,+1}; either may be NULL), for the bit-exact check. */
 int cmm_frobenius_signs(cmm_ctx* ctx, int64_t n1, int64_t n3, int32_t d, uint64_t seed,
                         int8_t* s1, int8_t* s2);
+
+/* ---- sublinear extraction (Section 4, Figure 3) ----------------------- */
+
+/* FINDSIGNIFICANTENTRIES(delta): positions (i, j) of significant entries of
+ * AB.  Besides the sketch of AB, the library computes with the same hash
+ * functions the sketches of the submatrix products of eq. (3),
+ * (I_{E_r} A) B for the 2 L1 bits of the row code and A (B I_{E_r}) for the
+ * 2 L3 bits of the column code, where E(x) = bits(x) || not bits(x) over
+ * L = max(1, ceil(log2 n)) bits (the paper's expander code is not given;
+ * this complement code detects, not corrects, errors).  For every
+ * repetition t and bucket k the bit string [|p^(t,r)[k]| > delta/2] is
+ * decoded into (i, j), or rejected unless every bit pair is complementary;
+ * positions decoded in at least d/2 repetitions are returned, sorted by
+ * i*n3 + j, at most `cap` of them in out_i/out_j (host arrays), with
+ * *out_count the full number (call again with a larger cap if it exceeds
+ * cap).  Operands, dtype, scales, b, d, seed as in cmm_sketch_product_ex;
+ * flags: CMM_SUBTRACT_DIAG (the product with a zero diagonal).  main_out,
+ * if non-NULL, receives the sketch of AB itself (for DECOMPRESS of the
+ * returned positions); free it with cmm_sketch_free().  The work is
+ * 2 (L1 + L3) + 1 sketch products (Section 4: a factor O(lg n) more time for
+ * compression). */
+int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                         int64_t n1, int64_t m, int64_t n3, int32_t dtype, const float* scaleA,
+                         const float* scaleB, int64_t b, int32_t d, uint64_t seed, uint32_t flags,
+                         double delta, int64_t cap, int64_t* out_i, int64_t* out_j,
+                         int64_t* out_count, cmm_sketch** main_out);
 
 /* ---- decoding (DECOMPRESS, Figure 1) ---------------------------------- */
 

@@ -82,6 +82,9 @@ _SIGS = {
     "cmm_frobenius_bound": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P, _I32,
                                       _U64, _U32, _P, C.POINTER(C.c_double)]),
     "cmm_frobenius_signs": (C.c_int, [_P, _I64, _I64, _I32, _U64, _P, _P]),
+    "cmm_find_significant": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P, _I64,
+                                       _I32, _U64, _U32, C.c_double, _I64, _P, _P,
+                                       C.POINTER(_I64), C.POINTER(_P)]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -333,6 +336,20 @@ def cmm_frobenius_signs(ctx, n1, n3, d, seed):
     return s1, s2
 
 
+def cmm_find_significant(ctx, A, lda, B, ldb, n1, m, n3, dtype, scaleA, scaleB, b, d, seed,
+                         flags, delta, cap=1 << 16, want_sketch=False):
+    """Returns (i, j, total_count, sketch handle or None)."""
+    oi = np.empty(max(cap, 1), np.int64); oj = np.empty(max(cap, 1), np.int64)
+    cnt = _I64(); sk = _P()
+    _check(load().cmm_find_significant(ctx, _ptr(A), lda, _ptr(B), ldb, n1, m, n3, dtype,
+                                       _ptr(scaleA), _ptr(scaleB), b, d, seed, flags, delta, cap,
+                                       oi.ctypes.data_as(_P), oj.ctypes.data_as(_P), C.byref(cnt),
+                                       C.byref(sk) if want_sketch else None),
+           "cmm_find_significant", ctx)
+    k = min(cnt.value, cap)
+    return oi[:k], oj[:k], cnt.value, (sk if want_sketch else None)
+
+
 # ------------------------------------------------------------- object layer
 
 class Context:
@@ -504,3 +521,21 @@ def frobenius_bound(ctx: Context, At, B, d: int, seed: int = 0, dtype: str = "f3
     return cmm_frobenius_bound(ctx.handle, At, At.stride(0), B, B.stride(0), n1_, m_, n3_,
                                DTYPES[dtype], scaleA, scaleB, d, seed,
                                CMM_SUBTRACT_DIAG if subtract_diag else 0)
+
+
+def find_significant(ctx: Context, At, B, b: int, d: int, delta: float, seed: int = 0,
+                     dtype: str = "f32", scaleA=None, scaleB=None, subtract_diag: bool = False,
+                     cap: int = 1 << 16, want_sketch: bool = False, n1: int | None = None,
+                     n3: int | None = None, m: int | None = None):
+    """FINDSIGNIFICANTENTRIES(delta) over the k-major device arrays At, B;
+    returns (i, j, total_count[, Sketch of AB])."""
+    m_ = m if m is not None else At.shape[0]
+    n1_ = n1 if n1 is not None else At.shape[1]
+    n3_ = n3 if n3 is not None else B.shape[1]
+    i, j, total, h = cmm_find_significant(ctx.handle, At, At.stride(0), B, B.stride(0), n1_, m_, n3_,
+                                          DTYPES[dtype], scaleA, scaleB, b, d, seed,
+                                          CMM_SUBTRACT_DIAG if subtract_diag else 0, delta, cap,
+                                          want_sketch)
+    if want_sketch:
+        return i, j, total, Sketch(h, ctx)
+    return i, j, total

@@ -1476,4 +1476,133 @@ int cmm_frobenius_bound(cmm_ctx* ctx, const void* A, int64_t lda, const void* B,
   return CMM_OK;
 }
 
+int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                         int64_t n1, int64_t m, int64_t n3, int32_t dtype, const float* scaleA,
+                         const float* scaleB, int64_t b, int32_t d, uint64_t seed, uint32_t flags,
+                         double delta, int64_t cap, int64_t* out_i, int64_t* out_j,
+                         int64_t* out_count, cmm_sketch** main_out) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  if (main_out) *main_out = nullptr;
+  if (!out_count) return fail(ctx, CMM_EINVAL, "out_count is NULL");
+  *out_count = 0;
+  if (cap < 0 || (cap > 0 && (!out_i || !out_j))) return fail(ctx, CMM_EINVAL, "bad output arrays");
+  if (!(delta > 0.0) || !std::isfinite(delta)) return fail(ctx, CMM_EINVAL, "delta must be positive");
+  int rc = check_operands(ctx, A, lda, B, ldb, n1, m, n3, dtype, b, d);
+  if (rc) return rc;
+  if (flags & ~CMM_SUBTRACT_DIAG) return fail(ctx, CMM_EINVAL, "unknown flag");
+  if ((flags & CMM_SUBTRACT_DIAG) && n1 != n3) return fail(ctx, CMM_EINVAL, "CMM_SUBTRACT_DIAG needs n1 == n3");
+  if (dtype != CMM_FP8_E4M3 && (scaleA || scaleB))
+    return fail(ctx, CMM_EINVAL, "scales are only taken with CMM_FP8_E4M3");
+  CMM_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  auto code_bits = [](int64_t n) { int L = 1; while (L < 62 && (int64_t(1) << L) < n) ++L; return L; };
+  const int L1 = code_bits(n1), L3 = code_bits(n3);
+  const int64_t db = (int64_t)d * b;
+
+  cmm_sketch* sk = new cmm_sketch();
+  sk->ctx = ctx; sk->n1 = n1; sk->m = m; sk->n3 = n3; sk->b = b; sk->d = d; sk->log2b = ilog2(b);
+  sk->has_params = true;
+  params_from_seed(seed, d, sk->params);
+  if (!alloc_sketch(sk)) { delete sk; return fail(ctx, CMM_ENOMEM, "sketch allocation failed"); }
+  const Operands op{A, lda, B, ldb, dtype, scaleA, scaleB, flags & CMM_SUBTRACT_DIAG};
+  const cmm::Geometry g = make_geometry(b, d, m, lookup_tuning(ctx, n1, m, n3, b, d, dtype));
+  int64_t tsize = 1;
+  while (tsize < 2 * db) tsize <<= 1;
+  std::vector<int64_t> found;
+  uint32_t nfound = 0;
+  {
+    Work w(ctx);
+    float* cr = w.get<float>((size_t)2 * (L1 + L3) * db);
+    double* ctmp = w.get<double>((size_t)db);
+    float* mask = w.get<float>((size_t)std::max(n1, n3));
+    double* diagm = (flags & CMM_SUBTRACT_DIAG) ? w.get<double>((size_t)n1) : nullptr;
+    int64_t* keys = w.get<int64_t>((size_t)db);
+    unsigned long long* tkeys = w.get<unsigned long long>((size_t)tsize);
+    uint32_t* tcnt = w.get<uint32_t>((size_t)tsize);
+    int64_t* outk = w.get<int64_t>((size_t)std::max<int64_t>(cap, 1));
+    uint32_t* cnt = w.get<uint32_t>(1);
+    uint64_t* pdev = w.get<uint64_t>((size_t)d * 8);
+    if (!cr || !ctmp || !mask || ((flags & CMM_SUBTRACT_DIAG) && !diagm) || !keys || !tkeys || !tcnt ||
+        !outk || !cnt || !pdev) {
+      release_sketch(sk);
+      return fail(ctx, CMM_ENOMEM, "workspace allocation failed");
+    }
+    rc = CMM_OK;
+    if (hipMemcpyAsync(pdev, sk->params.data(), sizeof(uint64_t) * d * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+      rc = fail(ctx, CMM_EHIP, "parameter upload failed");
+    // the sketch of AB itself, keeping its workspace (layout, both count sketches)
+    WsSpec spec;
+    WsPtrs ptr;
+    std::vector<void*> owned;
+    for (int attempt = 0; attempt < 2 && rc == CMM_OK; ++attempt) {
+      spec = ws_spec(g, n1, n3, attempt == 1, op.flags);
+      ptr = WsPtrs();
+      rc = ws_alloc(ctx, spec, ptr, owned);
+      if (rc == CMM_OK) rc = enqueue_product(ctx, sk, op, g, spec, ptr, pdev, s);
+      if (rc == CMM_OK && (hipMemcpyAsync(ctx->pinned_u32, ptr.p[W_OFLOW], sizeof(int32_t),
+                                          hipMemcpyDeviceToHost, s) != hipSuccess ||
+                           hipStreamSynchronize(s) != hipSuccess))
+        rc = fail(ctx, CMM_EHIP, "stream synchronisation failed");
+      if (rc == CMM_OK && ctx->pinned_u32[0] != 0 && attempt == 0) { ws_release(ctx, owned); continue; }
+      break;
+    }
+    double2* tw64 = nullptr; float2* tw32 = nullptr;
+    if (rc == CMM_OK) rc = get_twiddles(ctx, b, &tw64, &tw32);
+    if (rc == CMM_OK) {
+      cmm::SideDesc side[2];
+      bind_sides(g, sk, op, spec, ptr, side);
+      const int64_t nn[2] = {n1, n3};
+      const int Ls[2] = {L1, L3};
+      const float* scl[2] = {scaleA, scaleB};
+      // the sketch of the product with side q's index weighted by code bit r
+      auto masked = [&](int q, int r, int64_t slot) -> int {
+        CMM_HIP(ctx, cmm::launch_code_mask((int)nn[q], Ls[q], r, scl[q], mask, s));
+        side[q].scale = mask;
+        CMM_HIP(ctx, cmm::launch_countsketch(dtype, g, side[q], s));
+        CMM_HIP(ctx, cmm::launch_fft_mac(g, side[0], side[1], tw32, (float2*)ptr.p[W_PPART], s));
+        CMM_HIP(ctx, cmm::launch_ifft(g, (float2*)ptr.p[W_PPART], (double2*)ptr.p[W_WORK0],
+                                      (double2*)ptr.p[W_WORK1], tw64, ctmp, s));
+        if (diagm) {
+          CMM_HIP(ctx, cmm::launch_code_mask_diag((int)n1, Ls[q], r, (const double*)ptr.p[W_DIAG], diagm, s));
+          CMM_HIP(ctx, cmm::launch_sub_diag(g, sk->hs1, sk->hs2, (int)n1, (int)n3, diagm, (int)n1, ctmp, s));
+        }
+        CMM_HIP(ctx, cmm::launch_to_f32(ctmp, cr + slot * db, db, s));
+        return CMM_OK;
+      };
+      Scope sc_(ctx, "extract");
+      // column-code sketches, then the row-code ones (B's sketch restored)
+      for (int r = 0; r < 2 * L3 && rc == CMM_OK; ++r) rc = masked(1, r, 2 * L1 + r);
+      if (rc == CMM_OK) {
+        side[1].scale = scaleB;
+        if (cmm::launch_countsketch(dtype, g, side[1], s) != hipSuccess) rc = fail(ctx, CMM_EHIP, "countsketch launch failed");
+      }
+      for (int r = 0; r < 2 * L1 && rc == CMM_OK; ++r) rc = masked(0, r, r);
+      if (rc == CMM_OK) {
+        hipError_t e = cmm::launch_extract_decode(cr, d, b, L1, L3, (int)n1, (int)n3, (float)(0.5 * delta), keys, s);
+        if (e == hipSuccess) e = cmm::launch_fill_i32((int32_t*)tkeys, 2 * tsize, -1, s);
+        if (e == hipSuccess) e = cmm::launch_fill_i32((int32_t*)tcnt, tsize, 0, s);
+        if (e == hipSuccess) e = cmm::launch_fill_i32((int32_t*)cnt, 1, 0, s);
+        if (e == hipSuccess) e = cmm::launch_vote(keys, db, tkeys, tcnt, tsize, d, outk, cnt, cap, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&nfound, cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = fail(ctx, CMM_EHIP, std::string("extraction failed: ") + hipGetErrorString(e));
+      }
+      if (rc == CMM_OK && nfound > 0 && cap > 0) {
+        found.resize((size_t)std::min<int64_t>(nfound, cap));
+        if (hipMemcpy(found.data(), outk, sizeof(int64_t) * found.size(), hipMemcpyDeviceToHost) != hipSuccess)
+          rc = fail(ctx, CMM_EHIP, "result copy failed");
+      }
+    }
+    (void)hipStreamSynchronize(s);
+    ws_release(ctx, owned);
+  }
+  if (rc != CMM_OK) { release_sketch(sk); return rc; }
+  std::sort(found.begin(), found.end());
+  for (size_t q = 0; q < found.size(); ++q) { out_i[q] = found[q] / n3; out_j[q] = found[q] % n3; }
+  *out_count = nfound;
+  if (main_out) *main_out = sk;
+  else release_sketch(sk);
+  return CMM_OK;
+}
+
 }  // extern "C"
