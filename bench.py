@@ -63,6 +63,7 @@ def parse():
     p.add_argument("--no-compare", action="store_true", help="skip the bf16 run of the same workload")
     p.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     p.add_argument("--no-extract", action="store_true", help="skip the sublinear-extraction measurement")
+    p.add_argument("--no-sparse", action="store_true", help="skip the sparse-operand measurement")
     p.add_argument("--no-autotune", action="store_true",
                    help="use the built-in geometry instead of tuning the size class first")
     p.add_argument("--copy-calibration", action="store_true",
@@ -231,6 +232,50 @@ def run_frobenius(ctx, w, steps):
             "bound": bound, "median_X2": bound / 32.0, "d": w.d}
 
 
+def run_sparse(ctx, w, steps):
+    """Sparse operands (Corollary 8): covariance of a 1 %-dense m-by-n
+    observation matrix with the same n, m, b, d, both operands its CSR rows;
+    the sparse call against the dense call on the densified matrix."""
+    import numpy as np
+    import torch
+    import paper_1108_1320_amd as cmm
+    import workloads as W
+    ptr, idx, val = W.sparse_observations(w.n1, w.m, 0.01, 4242)
+    dp, di, dv = (torch.from_numpy(ptr).cuda(), torch.from_numpy(idx).cuda(),
+                  torch.from_numpy(val).cuda())
+    dense = np.zeros((w.m, w.n1), np.float32)
+    for k in range(w.m):
+        dense[k, idx[ptr[k]:ptr[k + 1]]] = val[ptr[k]:ptr[k + 1]]
+    dA = torch.from_numpy(dense).cuda()
+    dB = dA.clone()
+
+    def timed(fn):
+        fn().free()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn().free()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        cs = ctx.profile_read("countsketch")
+        ctx.profile(False)
+        return ms, cs[0] / max(cs[1], 1)
+    ms_s, cs_s = timed(lambda: cmm.sketch_product_sparse(ctx, dp, di, dv, dp, di, dv, w.n1, w.m, w.n1,
+                                                        w.b, w.d, seed=w.seed, subtract_diag=True))
+    ms_d, cs_d = timed(lambda: cmm.sketch_product(ctx, dA, dB, w.b, w.d, seed=w.seed, subtract_diag=True))
+    same = np.array_equal
+    a = cmm.sketch_product_sparse(ctx, dp, di, dv, dp, di, dv, w.n1, w.m, w.n1, w.b, w.d, seed=w.seed)
+    bd = cmm.sketch_product(ctx, dA, dB, w.b, w.d, seed=w.seed)
+    identical = bool(same(a.c(), bd.c()))
+    a.free(); bd.free()
+    nnz = int(ptr[-1])
+    return {"workload": f"covariance n=m={w.n1}, 1 % dense ({nnz} entries per operand), b={w.b}, d={w.d}",
+            "sparse_sketch_ms": round(ms_s, 4), "dense_sketch_ms": round(ms_d, 4),
+            "sparse_countsketch_ms": round(cs_s, 4), "dense_countsketch_ms": round(cs_d, 4),
+            "sketch_identical_to_dense": identical}
+
+
 def run_extract(ctx, w, median_x2):
     """FINDSIGNIFICANTENTRIES (Section 4) on the same operands: delta = 3 x
     the Frobenius estimate sqrt(median X^2) / sqrt(b); time of one call
@@ -389,6 +434,8 @@ def main():
         },
     }
     out["frobenius_bound"] = run_frobenius(ctx, w, args.steps)
+    if not args.no_sparse and args.workload == 2:
+        out["sparse_form"] = run_sparse(ctx, w, args.steps)
     if not args.no_extract and w.mode != "column":
         out["find_significant"] = run_extract(ctx, w, out["frobenius_bound"]["median_X2"])
     c_ref = None

@@ -153,6 +153,23 @@ int cmm_sketch_product_tables(cmm_ctx* ctx, const void* A, int64_t lda, const vo
                               const int32_t* h1, const int8_t* s1, const int32_t* h2,
                               const int8_t* s2, uint32_t flags, cmm_sketch** out);
 
+/* Sparse operands (Corollary 8: the count sketches cost O(N) for N
+ * non-zeros): A by columns (column k of A: row indices a_idx[e] and values
+ * a_val[e] for e in [a_ptr[k], a_ptr[k+1])) and B by rows (row k of B:
+ * column indices b_idx[e], values b_val[e], e in [b_ptr[k], b_ptr[k+1])).
+ * All device arrays; a_ptr and b_ptr have m + 1 entries starting at 0;
+ * indices lie in [0, n1) resp. [0, n3) and are distinct within a column
+ * (row); values are float32.  The result equals cmm_sketch_product_ex on
+ * the dense matrices (same hashing, same sketch; it is the same computation
+ * from the staged row on).  Offsets and index ranges are checked on the
+ * device first (CMM_EINVAL); repeated indices are not detected.  An operand
+ * without entries may pass NULL index and value arrays.  flags:
+ * CMM_SUBTRACT_DIAG (n1 == n3), CMM_ASYNC. */
+int cmm_sketch_product_sparse(cmm_ctx* ctx, const int64_t* a_ptr, const int32_t* a_idx,
+                              const float* a_val, const int64_t* b_ptr, const int32_t* b_idx,
+                              const float* b_val, int64_t n1, int64_t m, int64_t n3, int64_t b,
+                              int32_t d, uint64_t seed, uint32_t flags, cmm_sketch** out);
+
 int cmm_sketch_free(cmm_sketch* sk);
 
 /* Dimensions of a sketch (any output pointer may be NULL). */

@@ -82,6 +82,8 @@ _SIGS = {
     "cmm_frobenius_bound": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P, _I32,
                                       _U64, _U32, _P, C.POINTER(C.c_double)]),
     "cmm_frobenius_signs": (C.c_int, [_P, _I64, _I64, _I32, _U64, _P, _P]),
+    "cmm_sketch_product_sparse": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _I64, _I64, _I64, _I32,
+                                            _U64, _U32, C.POINTER(_P)]),
     "cmm_find_significant": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P, _I64,
                                        _I32, _U64, _U32, C.c_double, _I64, _P, _P,
                                        C.POINTER(_I64), C.POINTER(_P)]),
@@ -539,3 +541,15 @@ def find_significant(ctx: Context, At, B, b: int, d: int, delta: float, seed: in
     if want_sketch:
         return i, j, total, Sketch(h, ctx)
     return i, j, total
+
+
+def sketch_product_sparse(ctx: Context, a_ptr, a_idx, a_val, b_ptr, b_idx, b_val, n1: int, m: int,
+                          n3: int, b: int, d: int, seed: int = 0, subtract_diag: bool = False) -> Sketch:
+    """Sketch of AB from sparse device operands: A by columns (CSC: a_ptr
+    int64 [m+1], a_idx int32, a_val float32) and B by rows (CSR)."""
+    out = _P()
+    _check(load().cmm_sketch_product_sparse(ctx.handle, _ptr(a_ptr), _ptr(a_idx), _ptr(a_val),
+                                            _ptr(b_ptr), _ptr(b_idx), _ptr(b_val), n1, m, n3, b, d,
+                                            seed, CMM_SUBTRACT_DIAG if subtract_diag else 0,
+                                            C.byref(out)), "cmm_sketch_product_sparse", ctx.handle)
+    return Sketch(out, ctx)

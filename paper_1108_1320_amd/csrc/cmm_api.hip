@@ -337,6 +337,9 @@ int check_operands(cmm_ctx* c, const void* A, int64_t lda, const void* B, int64_
 struct Operands {
   const void* A; int64_t lda; const void* B; int64_t ldb;
   int32_t dtype; const float* scaleA; const float* scaleB; uint32_t flags;
+  // sparse operands (dtype kSparseF32): A by columns, B by rows
+  const int64_t* aptr = nullptr; const int32_t* aidx = nullptr;
+  const int64_t* bptr = nullptr; const int32_t* bidx = nullptr;
 };
 
 // Side descriptors of a product over the buffers `ptr` (which may be larger
@@ -352,6 +355,8 @@ void bind_sides(const cmm::Geometry& g, const cmm_sketch* sk, const Operands& op
     const int o = q * (W_CNT1 - W_CNT0);
     cmm::SideDesc& sd = side[q];
     sd.X = X[q]; sd.ld = ld[q]; sd.scale = sc[q]; sd.n = (int)nn[q]; sd.hs = hsv[q];
+    sd.sptr = q == 0 ? op.aptr : op.bptr;
+    sd.sidx = q == 0 ? op.aidx : op.bidx;
     sd.Lcap = spec.Lcap[q];
     sd.Lrow = g.W * sd.Lcap;
     sd.cnt = (int32_t*)ptr.p[W_CNT0 + o];
@@ -481,7 +486,8 @@ int product_common(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int6
                    int64_t n1, int64_t m, int64_t n3, int32_t dtype, const float* scaleA,
                    const float* scaleB, int64_t b, int32_t d, uint64_t seed,
                    const uint64_t* hash_params, const int32_t* th1, const int8_t* ts1,
-                   const int32_t* th2, const int8_t* ts2, uint32_t flags, cmm_sketch** out) {
+                   const int32_t* th2, const int8_t* ts2, uint32_t flags, cmm_sketch** out,
+                   const Operands* sparse = nullptr) {
   if (!valid_ctx(ctx)) return CMM_EINVAL;
   if (!out) return fail(ctx, CMM_EINVAL, "out is NULL");
   *out = nullptr;
@@ -533,7 +539,11 @@ int product_common(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int6
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) { cmm_sketch_free(sk); return fail(ctx, CMM_EHIP, "table upload failed"); }
   }
   bool over = false;
-  const Operands op{A, lda, B, ldb, dtype, scaleA, scaleB, flags};
+  Operands op{A, lda, B, ldb, dtype, scaleA, scaleB, flags};
+  if (sparse) {
+    op.dtype = cmm::kSparseF32;
+    op.aptr = sparse->aptr; op.aidx = sparse->aidx; op.bptr = sparse->bptr; op.bidx = sparse->bidx;
+  }
   const cmm::Tuning tu = lookup_tuning(ctx, n1, m, n3, b, d, dtype);
   rc = run_product(ctx, sk, op, tu, false, &over);
   if (rc == CMM_OK && over) rc = run_product(ctx, sk, op, tu, true, &over);
@@ -908,7 +918,8 @@ int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out) {
     delete c;
     return CMM_ENOMEM;
   }
-  if (cmm::prepare_countsketch() != hipSuccess || cmm::prepare_fft_mac() != hipSuccess) {
+  if (cmm::prepare_countsketch() != hipSuccess || cmm::prepare_fft_mac() != hipSuccess ||
+      cmm::prepare_sparse() != hipSuccess) {
     hipHostFree(c->pinned_u32);
     delete c;
     return CMM_EHIP;
@@ -1603,6 +1614,49 @@ int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B
   if (main_out) *main_out = sk;
   else release_sketch(sk);
   return CMM_OK;
+}
+
+int cmm_sketch_product_sparse(cmm_ctx* ctx, const int64_t* a_ptr, const int32_t* a_idx,
+                              const float* a_val, const int64_t* b_ptr, const int32_t* b_idx,
+                              const float* b_val, int64_t n1, int64_t m, int64_t n3, int64_t b,
+                              int32_t d, uint64_t seed, uint32_t flags, cmm_sketch** out) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  if (!out) return fail(ctx, CMM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!a_ptr || !b_ptr) return fail(ctx, CMM_EINVAL, "sparse offsets must be device pointers");
+  if (m <= 0 || m > (1 << 30)) return fail(ctx, CMM_EINVAL, "m out of range");
+  CMM_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  {
+    // offsets from 0, non-decreasing; every index inside its dimension
+    Work w(ctx);
+    int32_t* bad = w.get<int32_t>(1);
+    if (!bad) return fail(ctx, CMM_ENOMEM, "workspace allocation failed");
+    int64_t nnz[2] = {0, 0};
+    CMM_HIP(ctx, hipMemcpyAsync(&nnz[0], a_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CMM_HIP(ctx, hipMemcpyAsync(&nnz[1], b_ptr + m, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    CMM_HIP(ctx, hipStreamSynchronize(s));
+    if (nnz[0] < 0 || nnz[1] < 0) return fail(ctx, CMM_EINVAL, "negative entry count");
+    if ((nnz[0] > 0 && (!a_idx || !a_val)) || (nnz[1] > 0 && (!b_idx || !b_val)))
+      return fail(ctx, CMM_EINVAL, "sparse indices and values must be device pointers");
+    CMM_HIP(ctx, cmm::launch_fill_i32(bad, 1, 0, s));
+    if (n1 > 0 && n3 > 0) {
+      CMM_HIP(ctx, cmm::launch_sparse_check(a_ptr, a_idx, (int)m, (int)n1, nnz[0], bad, s));
+      CMM_HIP(ctx, cmm::launch_sparse_check(b_ptr, b_idx, (int)m, (int)n3, nnz[1], bad, s));
+    }
+    int32_t hbad = 0;
+    CMM_HIP(ctx, hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    CMM_HIP(ctx, hipStreamSynchronize(s));
+    if (hbad) return fail(ctx, CMM_EINVAL, "sparse offsets decrease or an index is out of range");
+  }
+  Operands sp{a_val, n1, b_val, n3, CMM_F32, nullptr, nullptr, flags};
+  sp.aptr = a_ptr; sp.aidx = a_idx; sp.bptr = b_ptr; sp.bidx = b_idx;
+  // an operand without entries may have NULL index and value arrays (never
+  // read); the offsets stand in for the value pointer in the generic checks
+  const void* av = a_val ? (const void*)a_val : (const void*)a_ptr;
+  const void* bv = b_val ? (const void*)b_val : (const void*)b_ptr;
+  return product_common(ctx, av, n1, bv, n3, n1, m, n3, CMM_F32, nullptr, nullptr, b, d, seed,
+                        nullptr, nullptr, nullptr, nullptr, nullptr, flags, out, &sp);
 }
 
 }  // extern "C"

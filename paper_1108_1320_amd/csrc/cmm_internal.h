@@ -94,9 +94,15 @@ constexpr int kMaxLog2C = 13;          // FFT row length C <= 8192
 constexpr int kTopkCap = 4096;         // candidates sorted by the final top-K pass
 constexpr int kMaxKPerBlock = 128;     // k per FFT block (float32 partial sums)
 
+// Element type codes of a stored operand: 0 f32, 1 bf16, 2 fp8 e4m3fn, and
+// 3 sparse f32 (row k's entries at sptr[k] .. sptr[k+1] of sidx / X).
+constexpr int kSparseF32 = 3;
+
 struct SideDesc {
-  const void* X;        // stored operand (k-major rows of length n)
-  int64_t ld;           // row stride in elements
+  const void* X;        // stored operand (k-major rows of length n); sparse: the values
+  int64_t ld;           // row stride in elements (dense)
+  const int64_t* sptr = nullptr;   // sparse: row offsets [m + 1]
+  const int32_t* sidx = nullptr;   // sparse: index of each entry in [0, n)
   const float* scale;   // per-element-position scale (fp8) or nullptr
   int n;                // hashed dimension (n1 or n3)
   int32_t* hs;          // [d][n]
@@ -178,6 +184,9 @@ hipError_t launch_extract_decode(const float* c, int d, int64_t b, int L1, int L
 hipError_t launch_vote(const int64_t* keys, int64_t nkeys, unsigned long long* tkeys,
                        uint32_t* tcnt, int64_t tsize, int d, int64_t* out, uint32_t* count,
                        int64_t cap, hipStream_t s);
+hipError_t launch_sparse_check(const int64_t* ptr, const int32_t* idx, int m, int n, int64_t nnz,
+                               int32_t* bad, hipStream_t s);
+hipError_t prepare_sparse();
 hipError_t launch_fill_random(void* X, int64_t count, int dtype, uint64_t seed, hipStream_t s);
 
 struct DecodeDesc {

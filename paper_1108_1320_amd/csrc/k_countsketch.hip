@@ -53,7 +53,7 @@ template <int DT>
 __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, int m, int W, int kblock) {
   extern __shared__ float row[];
   __shared__ uint32_t smax[2][64];
-  typedef Elem<DT> E;
+  typedef Elem<DT == kSparseF32 ? 0 : DT> E;
   typedef typename E::S S;
   const int tid = threadIdx.x;
   const int n = sd.n;
@@ -64,6 +64,14 @@ __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, 
   if (tid < 128) smax[tid >> 6][tid & 63] = 0u;
   int par = 0;
   for (int k = k0; k < k1; ++k, par ^= 1) {
+    if constexpr (DT == kSparseF32) {
+      // sparse row: zero the staged row, then scatter the row's entries
+      for (int x = tid; x < n; x += kCsThreads) row[x] = 0.0f;
+      __syncthreads();
+      const int64_t e1 = sd.sptr[k + 1];
+      for (int64_t e = sd.sptr[k] + tid; e < e1; e += kCsThreads) row[sd.sidx[e]] = X[e];
+      __syncthreads();
+    } else {
     const S* xr = X + (int64_t)k * sd.ld;
     // the row's first `head` elements are staged one by one, the body four at
     // a time from an address aligned to four elements, then the tail
@@ -93,6 +101,7 @@ __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, 
     for (int x = head + 4 * n4 + tid; x < n; x += kCsThreads)
       row[x] = E::one(xr[x]) * (sd.scale ? sd.scale[x] : 1.0f);
     __syncthreads();
+    }
     for (int t = 0; t < d; ++t) {
       const int L = sd.lseg[t];
       const int L4 = L >> 2;
@@ -150,8 +159,10 @@ hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStr
     hipLaunchKernelGGL(k_countsketch<0>, dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock);
   else if (dtype == 1)
     hipLaunchKernelGGL(k_countsketch<1>, dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock);
-  else
+  else if (dtype == 2)
     hipLaunchKernelGGL(k_countsketch<2>, dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock);
+  else
+    hipLaunchKernelGGL(k_countsketch<kSparseF32>, dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock);
   return hipGetLastError();
 }
 
@@ -161,7 +172,8 @@ hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStr
 hipError_t prepare_countsketch() {
   const void* fns[] = {reinterpret_cast<const void*>(&k_countsketch<0>),
                        reinterpret_cast<const void*>(&k_countsketch<1>),
-                       reinterpret_cast<const void*>(&k_countsketch<2>)};
+                       reinterpret_cast<const void*>(&k_countsketch<2>),
+                       reinterpret_cast<const void*>(&k_countsketch<kSparseF32>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     if (e != hipSuccess) return e;

@@ -166,8 +166,69 @@ __global__ __launch_bounds__(64) void k_diag_reduce(const double* __restrict__ p
   diag[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
+// diag[i] = sum_k A[i,k] B[k,i] for sparse A (by columns k) and B (by rows
+// k): one block per k stages column k of A in LDS (zeroed, then scattered)
+// and adds the float64 products with the entries of row k of B (float64
+// atomics: the summation order is not fixed).
+__global__ void k_diag_sparse(const int64_t* __restrict__ aptr, const int32_t* __restrict__ aidx,
+                              const float* __restrict__ aval, const int64_t* __restrict__ bptr,
+                              const int32_t* __restrict__ bidx, const float* __restrict__ bval,
+                              int m, int n, double* __restrict__ diag) {
+  extern __shared__ float col[];
+  for (int k = blockIdx.x; k < m; k += gridDim.x) {
+    for (int x = threadIdx.x; x < n; x += blockDim.x) col[x] = 0.0f;
+    __syncthreads();
+    for (int64_t e = aptr[k] + threadIdx.x; e < aptr[k + 1]; e += blockDim.x) col[aidx[e]] = aval[e];
+    __syncthreads();
+    for (int64_t e = bptr[k] + threadIdx.x; e < bptr[k + 1]; e += blockDim.x) {
+      const int j = bidx[e];
+      if (j < n && col[j] != 0.0f) atomicAdd(&diag[j], (double)col[j] * (double)bval[e]);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_f64(double* __restrict__ p, int64_t count) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+// Sparse operand check: offsets non-decreasing from 0, every index in [0, n).
+__global__ void k_sparse_check(const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                               int m, int n, int32_t* __restrict__ bad) {
+  const int64_t nnz = ptr[m];
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < (int64_t)m + nnz;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    if (q < m) {
+      if (ptr[q] > ptr[q + 1] || (q == 0 && ptr[0] != 0)) *bad = 1;
+    } else {
+      const int32_t v = idx[q - m];
+      if (v < 0 || v >= n) *bad = 1;
+    }
+  }
+}
+
+hipError_t launch_sparse_check(const int64_t* ptr, const int32_t* idx, int m, int n, int64_t nnz,
+                               int32_t* bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_sparse_check, dim3(grid_for((int64_t)m + nnz)), dim3(256), 0, s, ptr, idx, m,
+                     n, bad);
+  return hipGetLastError();
+}
+
+hipError_t prepare_sparse() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_diag_sparse),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+}
+
 hipError_t launch_diag(int dtype, const SideDesc& a, const SideDesc& bs, int m, int n,
                        double* partial, int kchunks, double* diag, hipStream_t s) {
+  if (dtype == kSparseF32) {
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(n)), dim3(256), 0, s, diag, (int64_t)n);
+    hipLaunchKernelGGL(k_diag_sparse, dim3(m < 4096 ? m : 4096), dim3(256), (size_t)n * sizeof(float), s,
+                       a.sptr, a.sidx, (const float*)a.X, bs.sptr, bs.sidx, (const float*)bs.X, m, n, diag);
+    return hipGetLastError();
+  }
   dim3 grid((n + 255) / 256, kchunks);
   if (dtype == 0)
     hipLaunchKernelGGL(k_diag_partial<0>, grid, dim3(256), 0, s, a.X, a.ld, a.scale, bs.X, bs.ld, bs.scale, m, n, kchunks, partial);

@@ -37,7 +37,7 @@ import numpy as np
 __all__ = [
     "rng", "covariance_observations", "dct2_orthonormal", "transform_operands",
     "bf16_encode", "e4m3fn_encode", "e4m3fn_grid", "Workload", "make_workload",
-    "CONFIGS", "batched_sizes", "batched_workloads", "next_pow2",
+    "CONFIGS", "batched_sizes", "batched_workloads", "sparse_observations", "next_pow2",
 ]
 
 
@@ -290,3 +290,18 @@ def batched_workloads(count: int = 64, seed: int = 1005, lo: int = 512, hi: int 
         out.append(covariance_workload(f"cfg5.{p}", n, n, pairs, (0.5, 0.95), b, d, pairs, dtype,
                                        data_seed, hash_seed))
     return out
+
+
+def sparse_observations(n: int, m: int, density: float, seed: int):
+    """m-by-n sparse observation matrix in CSR form (indptr int64, indices
+    int32, data float32 N(0,1)): each row holds round(density * n) distinct
+    random variables.  For a covariance product both operands are these rows
+    (A = X^T by columns k is X by rows k)."""
+    g = rng(seed)
+    per = max(1, int(round(density * n)))
+    indptr = np.arange(m + 1, dtype=np.int64) * per
+    indices = np.empty(m * per, dtype=np.int32)
+    for k in range(m):
+        indices[k * per:(k + 1) * per] = np.sort(g.choice(n, per, replace=False))
+    data = g.standard_normal(m * per).astype(np.float32)
+    return indptr, indices, data
