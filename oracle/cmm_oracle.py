@@ -397,6 +397,59 @@ def frobenius(A: np.ndarray, B: np.ndarray, d: int, seed: int, subtract_diag: bo
 
 
 # ---------------------------------------------------------------------------
+# number of non-zeros by doubling search (Section 5.1)
+# ---------------------------------------------------------------------------
+
+# Reading: the random diagonal matrices of Section 5.1 have entries uniform in
+# [1, 2): D1[i] = 1 + (z >> 11) 2^-53 with z the SplitMix64 output
+# 2^40 + i + 1 of the seed, D2[j] the same from output 2^41 + j + 1 (the
+# values are used in float32).  A bucket counts as zero when its magnitude is
+# at most zero_rel times the largest magnitude of its repetition (the float32
+# sketch is never exactly zero); b starts at 16, the smallest sketch length
+# the library takes, and doubles up to 2^20.
+
+NNZ_D1_OFFSET = 1 << 40
+NNZ_D2_OFFSET = 1 << 41
+
+
+def _splitmix64_at(seed: int, k: int) -> int:
+    """Output k (k >= 1) of SplitMix64 seeded with ``seed``."""
+    z = (seed + k * _GAMMA) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def nnz_weights(seed: int, n: int, offset: int) -> np.ndarray:
+    """Random diagonal entries in [1, 2), rounded to float32."""
+    w = [1.0 + (_splitmix64_at(seed, offset + x + 1) >> 11) * 2.0 ** -53 for x in range(n)]
+    return np.array(w, dtype=np.float32)
+
+
+def estimate_nnz(A: np.ndarray, B: np.ndarray, d: int, seed: int, zero_rel: float = 1e-5,
+                 b_max: int = 1 << 20, subtract_diag: bool = False):
+    """Doubling search of Section 5.1 on D1 A B D2: the first b (16, 32, ...)
+    at which at least 4b/5 buckets of the sketch are zero for every one of
+    the d hash functions; returns (b, zeros per repetition at that b), or
+    (-1, zeros at b_max) if no b up to b_max qualifies."""
+    n1, n3 = A.shape[0], B.shape[1]
+    D1 = nnz_weights(seed, n1, NNZ_D1_OFFSET).astype(np.float64)
+    D2 = nnz_weights(seed, n3, NNZ_D2_OFFSET).astype(np.float64)
+    As = np.asarray(A, np.float64) * D1[:, None]
+    Bs = np.asarray(B, np.float64) * D2[None, :]
+    b = 16
+    zeros = None
+    while b <= b_max:
+        c, _, _ = run(As, Bs, b, d, seed, subtract_diag=subtract_diag)
+        mx = np.abs(c).max(axis=1)
+        zeros = np.array([int(np.sum(np.abs(c[t]) <= zero_rel * mx[t])) for t in range(d)])
+        if np.all(5 * zeros >= 4 * b):
+            return b, zeros
+        b *= 2
+    return -1, zeros
+
+
+# ---------------------------------------------------------------------------
 # sublinear extraction of significant entries (Section 4, Figure 3)
 # ---------------------------------------------------------------------------
 

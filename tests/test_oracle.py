@@ -495,3 +495,39 @@ def test_masked_sketch_definition():
         np.testing.assert_allclose(cr[q] + cr[q + L1], whole, atol=1e-12)
     for q in range(L3):
         np.testing.assert_allclose(cc[q] + cc[q + L3], whole, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# number of non-zeros by doubling search (Section 5.1)
+# --------------------------------------------------------------------------
+
+def test_nnz_weights_range_and_stream():
+    w = O.nnz_weights(9, 50, O.NNZ_D1_OFFSET)
+    assert w.dtype == np.float32 and np.all(w >= 1.0) and np.all(w <= 2.0)
+    z = O.splitmix64(9, 3)
+    assert O._splitmix64_at(9, 3) == z[2]          # same stream definition
+    assert abs(float(O.nnz_weights(9, 1, 0)[0]) - (1.0 + (z[0] >> 11) * 2.0 ** -53)) < 1e-7
+
+
+@pytest.mark.parametrize("nnz", [5, 40, 300])
+def test_nnz_estimate_brackets_true_count(nnz):
+    """Section 5.1: the returned b is an upper bound on the number of
+    non-zeros (whp) and, since the search stops once b/5 exceeds it, at most
+    ten times it (doubling).  AB = S is formed from dense A and B (B =
+    pinv(A) S), so the non-zeros are the product's, not the operands'
+    structure: the random diagonal scaling keeps cancellation from hiding
+    or creating them."""
+    A, B, support = _sparse_product(80, 100, 90, nnz, nnz)
+    for seed in range(3):
+        b, zeros = O.estimate_nnz(A, B, 7, seed)
+        assert nnz <= b <= 10 * max(nnz, 2), (nnz, b)
+        assert np.all(5 * zeros >= 4 * b)
+
+
+def test_nnz_estimate_zero_product_and_dense_product():
+    g = np.random.default_rng(0)
+    A = g.standard_normal((30, 20)); Z = np.zeros((20, 25))
+    assert O.estimate_nnz(A, Z, 3, 1)[0] == 16
+    # a dense 30 x 25 product (750 non-zeros) needs b >= 750
+    b, _ = O.estimate_nnz(A, g.standard_normal((20, 25)), 3, 1)
+    assert 750 <= b <= 7500
