@@ -276,6 +276,30 @@ def run_sparse(ctx, w, steps):
             "sketch_identical_to_dense": identical}
 
 
+def run_nnz(ctx, w):
+    """Section 5.1 on the covariance of a 0.1 %-dense m-by-n observation
+    matrix (dense operands, same n, m, d): the returned b against the true
+    number of non-zeros of X^T X off the diagonal (scipy), and the time of
+    the whole doubling search."""
+    import numpy as np
+    import scipy.sparse as sps
+    import torch
+    import paper_1108_1320_amd as cmm
+    import workloads as W
+    ptr, idx, val = W.sparse_observations(w.n1, w.m, 0.001, 4343)
+    X = sps.csr_matrix((val, idx, ptr), shape=(w.m, w.n1))
+    Q = (X.T @ X).tocoo()
+    true_nnz = int(np.sum((Q.row != Q.col) & (Q.data != 0)))
+    dX = torch.from_numpy(X.toarray().astype(np.float32)).cuda()
+    dY = dX.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b, _ = cmm.estimate_nnz(ctx, dX, dY, w.d, seed=w.seed, subtract_diag=True)
+    torch.cuda.synchronize()
+    return {"workload": f"covariance n=m={w.n1}, 0.1 % dense, diagonal removed, d={w.d}",
+            "b": int(b), "true_nnz": true_nnz, "ms": round((time.perf_counter() - t0) * 1e3, 2)}
+
+
 def run_extract(ctx, w, median_x2):
     """FINDSIGNIFICANTENTRIES (Section 4) on the same operands: delta = 3 x
     the Frobenius estimate sqrt(median X^2) / sqrt(b); time of one call
@@ -436,6 +460,8 @@ def main():
     out["frobenius_bound"] = run_frobenius(ctx, w, args.steps)
     if not args.no_sparse and args.workload == 2:
         out["sparse_form"] = run_sparse(ctx, w, args.steps)
+    if not args.no_sparse and args.workload == 2:
+        out["nnz_estimate"] = run_nnz(ctx, w)
     if not args.no_extract and w.mode != "column":
         out["find_significant"] = run_extract(ctx, w, out["frobenius_bound"]["median_X2"])
     c_ref = None

@@ -112,7 +112,8 @@ const char* cmm_last_error(const cmm_ctx* ctx);
 /* Kernel timing: while enabled, the library records a pair of HIP events on
  * the context stream around every launch of the named kernels and sums
  * their durations.  `name` is one of "hash", "layout", "countsketch",
- * "fft_mac", "ifft", "decode", "frobenius" (cmm_frobenius_bound), "extract"
+ * "fft_mac", "ifft", "decode", "frobenius" (cmm_frobenius_bound), "nnz"
+ * (every product of cmm_estimate_nnz), "extract"
  * (the masked sketches, decoding and vote of cmm_find_significant), or
  * "batch" (a whole graph replay of
  * cmm_batch_run; the kernels inside a graph are not timed one by one).
@@ -280,6 +281,26 @@ int cmm_frobenius_bound(cmm_ctx* ctx, const void* A, int64_t lda, const void* B,
  * s2[d*n3] in {-1,+1}; either may be NULL), for the bit-exact check. */
 int cmm_frobenius_signs(cmm_ctx* ctx, int64_t n1, int64_t n3, int32_t d, uint64_t seed,
                         int8_t* s1, int8_t* s2);
+
+/* ---- number of non-zeros (Section 5.1) --------------------------------- */
+
+/* Doubling search for an upper bound on the number of non-zero entries of
+ * AB: the operands are scaled by random diagonal matrices D1 (rows of A)
+ * and D2 (columns of B), entries uniform in [1, 2) drawn from the seed's
+ * SplitMix64 stream at outputs 2^40 + i + 1 and 2^41 + j + 1 (so sums of
+ * non-zero entries do not cancel), and D1 A B D2 is sketched at b = 16, 32,
+ * ..., 2^20 with the hash functions of `seed`.  The search stops at the
+ * first b for which at least 4b/5 buckets are zero for all d hash functions
+ * (a bucket is zero when |c_t[u]| <= zero_rel * max_u |c_t[u]|; the float32
+ * sketch is never exactly 0); *b_out = that b, an upper bound on nnz(AB)
+ * with probability 1 - (3/4)^d and at most about 10 nnz(AB), or -1 if no
+ * b <= 2^20 qualifies.  zeros (host, d values, may be NULL) receives the
+ * zero counts of the last b tried.  Operands as in cmm_sketch_product_ex;
+ * flags: CMM_SUBTRACT_DIAG (count the product with a zero diagonal). */
+int cmm_estimate_nnz(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                     int64_t n1, int64_t m, int64_t n3, int32_t dtype, const float* scaleA,
+                     const float* scaleB, int32_t d, uint64_t seed, uint32_t flags, double zero_rel,
+                     int64_t* b_out, int64_t* zeros);
 
 /* ---- sublinear extraction (Section 4, Figure 3) ----------------------- */
 

@@ -84,6 +84,8 @@ _SIGS = {
     "cmm_frobenius_signs": (C.c_int, [_P, _I64, _I64, _I32, _U64, _P, _P]),
     "cmm_sketch_product_sparse": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _I64, _I64, _I64, _I64, _I32,
                                             _U64, _U32, C.POINTER(_P)]),
+    "cmm_estimate_nnz": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P, _I32, _U64,
+                                   _U32, C.c_double, C.POINTER(_I64), _P]),
     "cmm_find_significant": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P, _I64,
                                        _I32, _U64, _U32, C.c_double, _I64, _P, _P,
                                        C.POINTER(_I64), C.POINTER(_P)]),
@@ -553,3 +555,18 @@ def sketch_product_sparse(ctx: Context, a_ptr, a_idx, a_val, b_ptr, b_idx, b_val
                                             seed, CMM_SUBTRACT_DIAG if subtract_diag else 0,
                                             C.byref(out)), "cmm_sketch_product_sparse", ctx.handle)
     return Sketch(out, ctx)
+
+
+def estimate_nnz(ctx: Context, At, B, d: int, seed: int = 0, dtype: str = "f32", scaleA=None,
+                 scaleB=None, subtract_diag: bool = False, zero_rel: float = 1e-5,
+                 n1: int | None = None, n3: int | None = None, m: int | None = None):
+    """Doubling search of Section 5.1; returns (b, zeros per repetition at the last b)."""
+    m_ = m if m is not None else At.shape[0]
+    n1_ = n1 if n1 is not None else At.shape[1]
+    n3_ = n3 if n3 is not None else B.shape[1]
+    bo = _I64(); z = np.empty(d, np.int64)
+    _check(load().cmm_estimate_nnz(ctx.handle, _ptr(At), At.stride(0), _ptr(B), B.stride(0), n1_, m_,
+                                   n3_, DTYPES[dtype], _ptr(scaleA), _ptr(scaleB), d, seed,
+                                   CMM_SUBTRACT_DIAG if subtract_diag else 0, zero_rel, C.byref(bo),
+                                   z.ctypes.data_as(_P)), "cmm_estimate_nnz", ctx.handle)
+    return bo.value, z

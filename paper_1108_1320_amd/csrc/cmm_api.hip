@@ -1659,4 +1659,59 @@ int cmm_sketch_product_sparse(cmm_ctx* ctx, const int64_t* a_ptr, const int32_t*
                         nullptr, nullptr, nullptr, nullptr, nullptr, flags, out, &sp);
 }
 
+int cmm_estimate_nnz(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                     int64_t n1, int64_t m, int64_t n3, int32_t dtype, const float* scaleA,
+                     const float* scaleB, int32_t d, uint64_t seed, uint32_t flags, double zero_rel,
+                     int64_t* b_out, int64_t* zeros) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  if (!b_out) return fail(ctx, CMM_EINVAL, "b_out is NULL");
+  *b_out = -1;
+  int rc = check_operands(ctx, A, lda, B, ldb, n1, m, n3, dtype, 16, d);
+  if (rc) return rc;
+  if (flags & ~CMM_SUBTRACT_DIAG) return fail(ctx, CMM_EINVAL, "unknown flag");
+  if ((flags & CMM_SUBTRACT_DIAG) && n1 != n3) return fail(ctx, CMM_EINVAL, "CMM_SUBTRACT_DIAG needs n1 == n3");
+  if (dtype != CMM_FP8_E4M3 && (scaleA || scaleB))
+    return fail(ctx, CMM_EINVAL, "scales are only taken with CMM_FP8_E4M3");
+  if (!(zero_rel >= 0.0) || !(zero_rel < 1.0)) return fail(ctx, CMM_EINVAL, "zero_rel must be in [0, 1)");
+  CMM_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  Work w(ctx);
+  float* w1 = w.get<float>((size_t)n1);
+  float* w2 = w.get<float>((size_t)n3);
+  int64_t* zdev = w.get<int64_t>((size_t)d);
+  if (!w1 || !w2 || !zdev) return fail(ctx, CMM_ENOMEM, "workspace allocation failed");
+  // D1, D2: entries in [1, 2) from the seed's SplitMix64 stream at 2^40 and
+  // 2^41 (times the fp8 column scales)
+  CMM_HIP(ctx, cmm::launch_nnz_weights(seed, 1ull << 40, (int)n1, scaleA, w1, s));
+  CMM_HIP(ctx, cmm::launch_nnz_weights(seed, 1ull << 41, (int)n3, scaleB, w2, s));
+  const Operands op{A, lda, B, ldb, dtype, w1, w2, flags & CMM_SUBTRACT_DIAG};
+  std::vector<int64_t> zh((size_t)d);
+  for (int64_t b = 16; b <= (1 << 20); b *= 2) {
+    cmm_sketch* sk = new cmm_sketch();
+    sk->ctx = ctx; sk->n1 = n1; sk->m = m; sk->n3 = n3; sk->b = b; sk->d = d; sk->log2b = ilog2(b);
+    sk->has_params = true;
+    params_from_seed(seed, d, sk->params);
+    if (!alloc_sketch(sk)) { delete sk; return fail(ctx, CMM_ENOMEM, "sketch allocation failed"); }
+    bool over = false;
+    const cmm::Tuning tu = lookup_tuning(ctx, n1, m, n3, b, d, dtype);
+    {
+      Scope sc_(ctx, "nnz");
+      rc = run_product(ctx, sk, op, tu, false, &over);
+      if (rc == CMM_OK && over) rc = run_product(ctx, sk, op, tu, true, &over);
+      if (rc == CMM_OK && cmm::launch_nnz_zeros(sk->c64, d, b, zero_rel, zdev, s) != hipSuccess)
+        rc = fail(ctx, CMM_EHIP, "zero count launch failed");
+    }
+    if (rc == CMM_OK && (hipMemcpyAsync(zh.data(), zdev, sizeof(int64_t) * d, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                         hipStreamSynchronize(s) != hipSuccess))
+      rc = fail(ctx, CMM_EHIP, "zero count copy failed");
+    release_sketch(sk);
+    if (rc) return rc;
+    if (zeros) std::copy(zh.begin(), zh.end(), zeros);
+    bool done = true;
+    for (int t = 0; t < d; ++t) done = done && 5 * zh[t] >= 4 * b;
+    if (done) { *b_out = b; return CMM_OK; }
+  }
+  return CMM_OK;
+}
+
 }  // extern "C"

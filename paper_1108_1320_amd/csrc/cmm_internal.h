@@ -187,6 +187,10 @@ hipError_t launch_vote(const int64_t* keys, int64_t nkeys, unsigned long long* t
 hipError_t launch_sparse_check(const int64_t* ptr, const int32_t* idx, int m, int n, int64_t nnz,
                                int32_t* bad, hipStream_t s);
 hipError_t prepare_sparse();
+hipError_t launch_nnz_weights(uint64_t seed, uint64_t offset, int n, const float* scale, float* out,
+                              hipStream_t s);
+hipError_t launch_nnz_zeros(const double* c, int d, int64_t b, double rel, int64_t* zeros,
+                            hipStream_t s);
 hipError_t launch_fill_random(void* X, int64_t count, int dtype, uint64_t seed, hipStream_t s);
 
 struct DecodeDesc {
