@@ -137,10 +137,21 @@ template <int U> struct Batch {
   uint32_t u[U];
 };
 
-// Past the segment's end a lane gets value 0 and its own first slot.
+// Past the segment's end a lane gets value 0 and its own first slot.  A
+// batch wholly inside the segment (a wave-uniform test) is loaded without
+// per-entry tests.
 template <int G, int kU>
 __device__ __forceinline__ void fetch(Batch<kU>& bt, const float* sa, const uint32_t* en, int ls,
                                       int lane, int first, uint32_t own_off) {
+  if ((first + kU) * G <= ls) {
+#pragma unroll
+    for (int i = 0; i < kU; ++i) {
+      const int it = lane + G * (first + i);
+      bt.v[i] = sa[it];
+      bt.u[i] = en[it];
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < kU; ++i) {
     const int it = lane + G * (first + i);
