@@ -573,7 +573,7 @@ int check_dims(cmm_ctx* c, int64_t n1, int64_t m, int64_t n3, int64_t b, int32_t
 }
 
 // Mean time of one product under tuning `tu` on the synthetic operands of
-// `sk` (3 back-to-back runs after a warm-up run on the context stream).
+// `sk` (5 back-to-back runs after a warm-up run on the context stream).
 int time_candidate(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Tuning& tu,
                    const uint64_t* pdev, hipEvent_t ev0, hipEvent_t ev1, double* ms) {
   hipStream_t s = c->stream;
@@ -591,12 +591,12 @@ int time_candidate(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Tu
       rc = fail(c, CMM_EHIP, "stream synchronisation failed");
     if (rc == CMM_OK && c->pinned_u32[0] != 0 && attempt == 0) { ws_release(c, owned); continue; }
     if (rc == CMM_OK && hipEventRecord(ev0, s) != hipSuccess) rc = fail(c, CMM_EHIP, "event record failed");
-    for (int r = 0; r < 3 && rc == CMM_OK; ++r) rc = enqueue_product(c, sk, op, g, spec, ptr, pdev, s);
+    for (int r = 0; r < 5 && rc == CMM_OK; ++r) rc = enqueue_product(c, sk, op, g, spec, ptr, pdev, s);
     if (rc == CMM_OK && hipEventRecord(ev1, s) != hipSuccess) rc = fail(c, CMM_EHIP, "event record failed");
     if (rc == CMM_OK && hipEventSynchronize(ev1) != hipSuccess) rc = fail(c, CMM_EHIP, "event wait failed");
     float t = 0.f;
     if (rc == CMM_OK && hipEventElapsedTime(&t, ev0, ev1) != hipSuccess) rc = fail(c, CMM_EHIP, "event time failed");
-    if (rc == CMM_OK) *ms = t / 3.0;
+    if (rc == CMM_OK) *ms = t / 5.0;
     (void)hipStreamSynchronize(s);
     ws_release(c, owned);
     return rc;
@@ -606,8 +606,9 @@ int time_candidate(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Tu
 
 // Coordinate search over the geometry of one size class: the FFT row
 // length first, then the number of k per spectral block, then the number
-// of count-sketch blocks; candidates that give the same launch shapes as
-// one already timed are skipped.
+// of count-sketch blocks, starting from the built-in default; candidates
+// that give the same launch shapes as one already timed are skipped, and a
+// candidate replaces the incumbent only when at least 3 % faster.
 int autotune_class(cmm_ctx* c, int64_t n1, int64_t m, int64_t n3, int64_t b, int d, int dtype,
                    TuneEntry* best) {
   hipStream_t s = c->stream;
@@ -655,7 +656,9 @@ int autotune_class(cmm_ctx* c, int64_t n1, int64_t m, int64_t n3, int64_t b, int
       double ms = 0.0;
       rc = time_candidate(c, sk, op, t, pdev, ev0, ev1, &ms);
       if (rc != CMM_OK) break;
-      if (ms < cur_ms) { cur = t; cur_ms = ms; }
+      // a candidate must be clearly faster than the incumbent (timing noise
+      // between runs is a few per cent)
+      if (ms < 0.97 * cur_ms) { cur = t; cur_ms = ms; }
     }
   }
   c->prof = prof;
@@ -780,10 +783,19 @@ int build_batch(cmm_ctx* c, const cmm_problem* pr, int count, uint32_t flags, cm
     CMM_HIP(c, hipMemcpyAsync(pdev, sk->params.data(), sizeof(uint64_t) * p.d * 8,
                               hipMemcpyHostToDevice, s));
     if ((flags & CMM_AUTOTUNE) && !c->tuning.count(tune_key(p.n1, p.m, p.n3, p.b, p.d, p.dtype))) {
+      // tune the class on its largest problem (the one that costs most)
+      const TuneKey key = tune_key(p.n1, p.m, p.n3, p.b, p.d, p.dtype);
+      const cmm_problem* big = &p;
+      for (int q = i + 1; q < count; ++q) {
+        const cmm_problem& o = pr[q];
+        if (tune_key(o.n1, o.m, o.n3, o.b, o.d, o.dtype) < key || key < tune_key(o.n1, o.m, o.n3, o.b, o.d, o.dtype))
+          continue;
+        if ((double)o.n1 * o.m * o.n3 > (double)big->n1 * big->m * big->n3) big = &o;
+      }
       TuneEntry e;
-      int rc = autotune_class(c, p.n1, p.m, p.n3, p.b, p.d, p.dtype, &e);
+      int rc = autotune_class(c, big->n1, big->m, big->n3, big->b, big->d, big->dtype, &e);
       if (rc) return rc;
-      c->tuning[tune_key(p.n1, p.m, p.n3, p.b, p.d, p.dtype)] = e;
+      c->tuning[key] = e;
     }
     it[i].g = make_geometry(p.b, p.d, p.m, lookup_tuning(c, p.n1, p.m, p.n3, p.b, p.d, p.dtype));
     it[i].op = Operands{p.A, p.lda, p.B, p.ldb, p.dtype, p.scaleA, p.scaleB, p.flags};
