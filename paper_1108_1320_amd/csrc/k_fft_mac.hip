@@ -66,13 +66,11 @@ template <int L> struct FftShape {
   static constexpr int E = L % 4;
   static constexpr int S = L / 4 + (E ? 1 : 0);
   static constexpr int G = T < 64 ? T : 64;
-  // fold entries fetched per lane during the transform (U) and per later
-  // batch (US, 0: batches of U).  At L = 12, 17 entries per lane hold a whole
-  // wave segment of up to 1088 entries (n = b/16 gives segments of about
-  // 1000 +- 32), so no fetch waits after the transform.  L = 13 has 8 waves,
-  // half the entries each.
+  // fold entries per lane and batch.  At L = 12, 17 entries per lane hold a
+  // whole wave segment of up to 1088 entries (n = b/16 gives segments of
+  // about 1000 +- 32), so no fetch waits after the transform.  L = 13 has 8
+  // waves, half the entries each.
   static constexpr int U = L == 12 ? 17 : (L == 13 ? 4 : 8);
-  static constexpr int US = 0;
   static constexpr int span(int s) { return s == 0 ? 1 : (E ? (1 << E) : 16) * ipow16(s - 1); }
   static constexpr int radix(int s) { return (s == 0 && E) ? (1 << E) : 16; }
   // twiddle tables of the middle stages 1 .. S-2, one after the other:
@@ -196,57 +194,78 @@ template <typename V> __device__ __forceinline__ const V& at_byte(const V* base,
 // wave-uniform test; inside a group there is no branch, so the weight reads
 // issue together.  Padding entries carry value 0 and an own slot of the
 // wave.  Row 0 has unit weights (ROW0).
+template <int kU, bool ROW0>
+__device__ __forceinline__ void fold_group(const Batch<kU>& bt, int g0, unsigned long long* Z,
+                                           const float2* wf, float scale) {
+  constexpr int kG = 4;
+  const int gn = kU - g0 < kG ? kU - g0 : kG;
+  float2 w[kG];
+  if constexpr (!ROW0) {
+#pragma unroll
+    for (int i = 0; i < kG; ++i)
+      if (i < gn) w[i] = at_byte(wf, bt.u[g0 + i] >> 16);
+  }
+#pragma unroll
+  for (int i = 0; i < kG; ++i) {
+    if (i >= gn) break;
+    const uint32_t off = bt.u[g0 + i] & 0xFFFFu;
+    // |value * scale| < 2^30: float32 keeps 24 bits, so values near the top
+    // have no fraction and truncation only touches the smallest ones
+    const float sv = bt.v[g0 + i] * scale;
+    if constexpr (ROW0) atomicAdd(&at_byte(Z, off), (unsigned long long)(long long)(int)sv);
+    else atomicAdd(&at_byte(Z, off), pack2((int)(sv * w[i].x), (int)(sv * w[i].y)));
+  }
+}
+
 template <int G, int kU, bool ROW0>
 __device__ __forceinline__ void fold(const Batch<kU>& bt, unsigned long long* Z,
                                      const float2* wf, float scale, int ls, int first) {
 #pragma unroll
   for (int g0 = 0; g0 < kU; g0 += 4) {
     if ((first + g0) * G >= ls) break;
-    constexpr int kG = 4;
-    const int gn = kU - g0 < kG ? kU - g0 : kG;
-    float2 w[kG];
-    if constexpr (!ROW0) {
-#pragma unroll
-      for (int i = 0; i < kG; ++i)
-        if (i < gn) w[i] = at_byte(wf, bt.u[g0 + i] >> 16);
-    }
-#pragma unroll
-    for (int i = 0; i < kG; ++i) {
-      if (i >= gn) break;
-      const uint32_t off = bt.u[g0 + i] & 0xFFFFu;
-      // |value * scale| < 2^30: float32 keeps 24 bits, so values near the top
-      // have no fraction and truncation only touches the smallest ones
-      const float sv = bt.v[g0 + i] * scale;
-      if constexpr (ROW0) atomicAdd(&at_byte(Z, off), (unsigned long long)(long long)(int)sv);
-      else atomicAdd(&at_byte(Z, off), pack2((int)(sv * w[i].x), (int)(sv * w[i].y)));
-    }
+    fold_group<kU, ROW0>(bt, g0, Z, wf, scale);
   }
 }
 
-// The whole segment: batch `a` (kU entries per lane, fetched during the
-// previous transform) first, then batches of kS entries.  The first small
-// batch is fetched before `a` is folded, so its memory latency overlaps that
-// folding (a segment a little longer than kU entries per lane costs no
-// exposed fetch); later ones are fetched and folded in turn.  kS = 0: one
-// buffer of kU, fetched and folded in turn.
-template <int G, int kU, int kS, bool ROW0>
+// Entries g0 .. g0+3 (fewer in the last group) of batch `first` into the
+// same positions of `bt`; `whole`: the batch lies wholly inside the segment.
+template <int G, int kU>
+__device__ __forceinline__ void fetch_group(Batch<kU>& bt, int g0, const float* sa,
+                                            const uint32_t* en, int ls, int lane, int first,
+                                            uint32_t own_off, bool whole) {
+  constexpr int kG = 4;
+  const int gn = kU - g0 < kG ? kU - g0 : kG;
+#pragma unroll
+  for (int i = 0; i < kG; ++i) {
+    if (i >= gn) break;
+    const int it = lane + G * (first + g0 + i);
+    if (whole || it < ls) { bt.v[g0 + i] = sa[it]; bt.u[g0 + i] = en[it]; }
+    else { bt.v[g0 + i] = 0.0f; bt.u[g0 + i] = own_off; }
+  }
+}
+
+// The whole segment, batch by batch; batch `a` (kU entries per lane) was
+// fetched during the previous transform.  While a batch is folded, each
+// group's registers are refilled with the same group of the next batch
+// right after the group is folded, so the next batch's loads are in flight
+// behind the rest of the folding, with no second buffer.
+template <int G, int kU, bool ROW0>
 __device__ __forceinline__ void fold_all(Batch<kU>& a, unsigned long long* Z, const float2* wf,
                                          float scale, const float* sa, const uint32_t* en, int ls,
                                          int lane, uint32_t own_off) {
-  if constexpr (kS == 0) {
-    fold<G, kU, ROW0>(a, Z, wf, scale, ls, 0);
-    for (int first = kU; first * G < ls; first += kU) {
-      fetch<G, kU>(a, sa, en, ls, lane, first, own_off);
+  for (int first = 0;; first += kU) {
+    const int next = first + kU;
+    if (next * G < ls) {
+      // every group of this batch lies inside the segment
+      const bool whole = (next + kU) * G <= ls;
+#pragma unroll
+      for (int g0 = 0; g0 < kU; g0 += 4) {
+        fold_group<kU, ROW0>(a, g0, Z, wf, scale);
+        fetch_group<G, kU>(a, g0, sa, en, ls, lane, next, own_off, whole);
+      }
+    } else {
       fold<G, kU, ROW0>(a, Z, wf, scale, ls, first);
-    }
-  } else {
-    Batch<kS> s1;
-    int first = kU;
-    if (first * G < ls) fetch<G, kS>(s1, sa, en, ls, lane, first, own_off);
-    fold<G, kU, ROW0>(a, Z, wf, scale, ls, 0);
-    for (; first * G < ls; first += kS) {
-      if (first > kU) fetch<G, kS>(s1, sa, en, ls, lane, first, own_off);
-      fold<G, kS, ROW0>(s1, Z, wf, scale, ls, first);
+      break;
     }
   }
 }
@@ -331,8 +350,8 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) Z[own<T>(jbase, j, q)] = 0ull;
       __builtin_amdgcn_wave_barrier();
-      if (f1 == 0) fold_all<G, kU, F::US, true>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
-      else fold_all<G, kU, F::US, false>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      if (f1 == 0) fold_all<G, kU, true>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      else fold_all<G, kU, false>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
       // first batch of the next (side, k), in flight during the transform
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
       else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0, own_off);
