@@ -1169,11 +1169,11 @@ int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int6
     Scope sc_(c, "decode");
     // Fast path: a pass over every 16th row tile estimates a threshold T0
     // above which about 2K + 64 estimates lie; one full pass then builds the
-    // exact histogram of the top 12 key bits and keeps every candidate with
-    // key >= T0.  The exact histogram shows whether T0 is at or below the
+    // exact histogram of the top 12 key bits of the keys >= T0 and keeps
+    // those candidates.  The histogram shows whether T0 is at or below the
     // K-th key and whether the kept set is complete; otherwise the
-    // digit-by-digit passes below run (from the histogram already built).
-    bool have_level0 = false, done = false;
+    // digit-by-digit passes below run.
+    bool done = false;
     if (tiles >= 64) {
       CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
       CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 16, 0, 32, 19, 0xFFF, hist, 0, nullptr, nullptr, 0, s));
@@ -1197,7 +1197,7 @@ int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int6
         CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 1, 0, 32, 19, 0xFFF, hist, T0, wide, count, kWide, s));
         CMM_HIP(c, hipMemcpyAsync(h.data(), hist, 4096 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         CMM_HIP(c, hipStreamSynchronize(s));
-        have_level0 = true;
+        // h counts only keys >= T0 (bins b0 and up): exact there
         int64_t n0 = 0;
         for (int q = b0; q < 4096; ++q) n0 += h[q];
         if (n0 >= K && n0 <= kWide) {
@@ -1227,13 +1227,11 @@ int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int6
       uint32_t thresh = 0;
       bool found = false;
       for (int level = 0; level < 3 && !found; ++level) {
-        if (!(level == 0 && have_level0)) {
-          CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
-          CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 1, prefix, pshift, dshift[level], dmask[level], hist,
-                                           0, nullptr, nullptr, 0, s));
-          CMM_HIP(c, hipMemcpyAsync(h.data(), hist, 4096 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-          CMM_HIP(c, hipStreamSynchronize(s));
-        }
+        CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
+        CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 1, prefix, pshift, dshift[level], dmask[level], hist,
+                                         0, nullptr, nullptr, 0, s));
+        CMM_HIP(c, hipMemcpyAsync(h.data(), hist, 4096 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        CMM_HIP(c, hipStreamSynchronize(s));
         int64_t cum = 0;
         int bin = -1;
         for (int q = (int)dmask[level]; q >= 0; --q) {

@@ -50,6 +50,41 @@ __device__ __forceinline__ float estimate(const DecodeDesc& dd, const int32_t* a
   }
 }
 
+// The estimate of (i, j) if its magnitude can reach T, else NaN.  |median| >= T
+// needs at least ceil(d/2) of the d signed values >= T or at least as many
+// <= -T (for even d the larger middle value must reach T), so the values are
+// gathered one repetition at a time and the gathering stops once neither
+// count can get there; a surviving candidate's estimate is computed exactly
+// as estimate() does.
+template <int D>
+__device__ __forceinline__ float estimate_above(const DecodeDesc& dd, const int32_t* a1,
+                                                const int32_t* a2, float T) {
+  static_assert(D > 0, "fixed d only");
+  constexpr int need = (D + 1) / 2;
+  float x[D];
+  int hi = 0, lo = 0;
+#pragma unroll
+  for (int t = 0; t < D; ++t) {
+    const uint32_t u = (uint32_t)((a1[t] >> 1) + (a2[t] >> 1)) & dd.mask;
+    const float v = dd.c32[(int64_t)t * dd.b + u];
+    x[t] = ((a1[t] ^ a2[t]) & 1) ? -v : v;
+    hi += x[t] >= T;
+    lo += x[t] <= -T;
+    const int left = D - 1 - t;
+    if (hi + left < need && lo + left < need) return __uint_as_float(0x7FC00000u);
+  }
+#pragma unroll
+  for (int r = 0; r < D; ++r) {
+#pragma unroll
+    for (int q = (r & 1); q + 1 < D; q += 2) {
+      const float l = fminf(x[q], x[q + 1]), h = fmaxf(x[q], x[q + 1]);
+      x[q] = l; x[q + 1] = h;
+    }
+  }
+  if constexpr (D & 1) return x[(D - 1) / 2];
+  else return 0.5f * (x[D / 2 - 1] + x[D / 2]);
+}
+
 template <int D> struct HashVec {
   int32_t v[D > 0 ? D : 64];
 };
@@ -90,8 +125,9 @@ __device__ __forceinline__ bool in_domain(int mode, int i, int j, int n1, int n3
 
 // Histogram of one key digit over the candidates whose key matches
 // `prefix` under `pmask`, over every tile_stride-th tile of 16 rows (1 = the
-// whole domain).  With COLLECT, candidates with key >= thresh are also
-// appended to `cand` (at most `cap`; `count` keeps counting past it).
+// whole domain).  With COLLECT, only candidates with key >= thresh are
+// counted, and they are also appended to `cand` (at most `cap`; `count`
+// keeps counting past it).
 template <int D, bool COLLECT>
 __global__ __launch_bounds__(256) void k_topk_hist(DecodeDesc dd, int mode, int tile_stride,
                                                    uint32_t pmask, uint32_t prefix, int dshift,
@@ -113,17 +149,27 @@ __global__ __launch_bounds__(256) void k_topk_hist(DecodeDesc dd, int mode, int 
       if (!in_domain(mode, i, j, dd.n1, dd.n3)) continue;
       HashVec<D> h1;
       load_hash<D>(h1, dd.hs1, dd.n1, i, dd.d);
-      const float est = estimate<D>(dd, h1.v, h2.v, dd.d);
+      float est;
+      if constexpr (COLLECT && D > 0) {
+        est = estimate_above<D>(dd, h1.v, h2.v, __uint_as_float(thresh));
+        if (est != est) continue;   // cannot reach the threshold
+      } else {
+        est = estimate<D>(dd, h1.v, h2.v, dd.d);
+      }
       const uint32_t key = __float_as_uint(fabsf(est));
-      if ((key & pmask) == prefix) atomicAdd(&h[(key >> dshift) & dmask], 1u);
       if constexpr (COLLECT) {
+        // only keys >= thresh are counted (and kept): the bulk of the
+        // distribution, far below it, never touches the histogram
         if (key >= thresh) {
+          if ((key & pmask) == prefix) atomicAdd(&h[(key >> dshift) & dmask], 1u);
           const uint32_t slot = atomicAdd(count, 1u);
           if (slot < (uint32_t)cap) {
             TopkCand c; c.key = key; c.i = i; c.j = j; c.val = est;
             cand[slot] = c;
           }
         }
+      } else {
+        if ((key & pmask) == prefix) atomicAdd(&h[(key >> dshift) & dmask], 1u);
       }
     }
   }
