@@ -13,8 +13,11 @@ buffers holding the observation matrix.
 
 Prints one JSON line.  ``value`` is the input GB/s of the whole step:
 bytes(A) + bytes(B) as stored, divided by the step time.  The same workload
-is also run with bf16 operands (``bf16_same_workload``) and both are checked
-against the float64 oracle.
+is also run with its operands in the other two formats (``bf16_same_workload``
+and ``fp8_same_workload`` beside the float32 default): element rate, top-K
+overlap and planted recall against the headline run, and, with the oracle,
+each format's arithmetic error (against the float64 oracle of the values it
+multiplies) apart from its quantisation error.
 
 The batched form (``batched_form``; ``--workload 5`` makes it the headline):
 64 covariance products, n = m log-uniform in [512, 8192], b = next power of
@@ -60,7 +63,7 @@ def parse():
     p.add_argument("--dtype", default=None, help="override the workload's dtype (f32/bf16/fp8)")
     p.add_argument("--d", type=int, default=None, help="override the number of repetitions")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--no-compare", action="store_true", help="skip the bf16 run of the same workload")
+    p.add_argument("--no-compare", action="store_true", help="skip the runs of the same workload in the other operand formats")
     p.add_argument("--no-batched", action="store_true", help="skip the batched-form measurement")
     p.add_argument("--no-extract", action="store_true", help="skip the sublinear-extraction measurement")
     p.add_argument("--no-sparse", action="store_true", help="skip the sparse-operand measurement")
@@ -471,8 +474,14 @@ def main():
         fb = out["frobenius_bound"]
         fb["bound_over_true"] = round(fb["bound"] / out["parity"]["frobenius_norm_sq"], 3)
         fb["median_X2_over_true"] = round(fb["median_X2"] / out["parity"]["frobenius_norm_sq"], 4)
-    if not args.no_compare and w.dtype == "f32" and w.mode != "column":
-        out["bf16_same_workload"] = compare_bf16(ctx, args, w, c_ref, oi, oj, value)
+    if not args.no_compare and w.mode != "column":
+        # the same product in the other operand formats, each against the
+        # float64 oracle of its own dequantised operands (arithmetic error)
+        # and of the float32 operands (quantisation error), with top-K and
+        # planted recall compared to this run's
+        for dt in ("f32", "bf16", "fp8"):
+            if dt != w.dtype:
+                out[f"{dt}_same_workload"] = compare_format(ctx, args, w, dt, c_ref, oi, oj, value)
     if not args.no_batched:
         out["batched_form"] = run_batched(ctx, max(3, args.steps // 4), 1, not args.no_cpu)
     sk.free()
@@ -480,42 +489,47 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def compare_bf16(ctx, args, w32, c_ref, oi32, oj32, value32):
-    """The same product with its operands stored in bf16: throughput, error
-    against the float64 oracle of the float32 operands (quantisation plus
-    arithmetic), and agreement of its top-K with the float32 path."""
+def compare_format(ctx, args, w0, dtype, c_ref0, oi0, oj0, value0):
+    """The same product with its operands stored as ``dtype``: element rate
+    against this run, top-K overlap, planted recall, and (when the oracle
+    ran) its error split into arithmetic (GPU vs the float64 oracle of the
+    values it multiplies) and quantisation (oracle of those values vs the
+    oracle of the float32 operands)."""
     import numpy as np
     import workloads as W
-    store = W.bf16_encode(w32.At_store)
-    w = W.Workload(name=w32.name, n1=w32.n1, m=w32.m, n3=w32.n3, b=w32.b, d=w32.d, K=w32.K,
-                   dtype="bf16", mode=w32.mode, seed=w32.seed, subtract_diag=w32.subtract_diag,
-                   At_store=store, B_store=store, planted=w32.planted, same_operand=True)
+    from oracle import cmm_oracle as O
+    w = W.make_workload(args.workload, dtype=dtype)
+    w.d = w0.d
     if not args.no_autotune:
-        ctx.autotune(w.n1, w.m, w.n3, w.b, w.d, "bf16")
-    r = run_timed(ctx, w, max(5, args.steps // 2), 2)
+        ctx.autotune(w.n1, w.m, w.n3, w.b, w.d, dtype)
+    esz = {"f32": 4, "bf16": 2, "fp8": 1}
+    r = run_timed(ctx, w, max(3, args.steps // 2), 1)
     v = r["input_bytes"] / (r["ms"] * 1e-3) / 1e9
-    c16 = r["sketch"].c()
     oi, oj, _ = r["topk"]
-    both = set(zip(oi.tolist(), oj.tolist())) & set(zip(oi32.tolist(), oj32.tolist()))
-    res = {"value": round(v, 3), "unit": "GB/s", "ms_per_step": round(r["ms"], 4),
+    both = set(zip(oi.tolist(), oj.tolist())) & set(zip(oi0.tolist(), oj0.tolist()))
+    res = {"dtype": dtype, "value": round(v, 3), "unit": "GB/s", "ms_per_step": round(r["ms"], 4),
            "input_elements_per_s": round((w.n1 * w.m + w.m * w.n3) / (r["ms"] * 1e-3), 1),
-           "element_rate_vs_f32": round((v / 2.0) / (value32 / 4.0), 4),
-           "topk_overlap_with_f32": round(len(both) / w.K, 4),
+           "element_rate_vs_this_run": round((v / esz[dtype]) / (value0 / esz[w0.dtype]), 4),
+           f"topk_overlap_with_{w0.dtype}": round(len(both) / w.K, 4),
            "planted_recall": planted_recall(w, oi, oj),
-           "geometry": list(ctx.tuning(w.n1, w.m, w.n3, w.b, w.d, "bf16")),
+           "geometry": list(ctx.tuning(w.n1, w.m, w.n3, w.b, w.d, dtype)),
            "kernel_ms_per_step": {k: round(x[0] / max(x[1], 1), 4) for k, x in r["kern"].items()}}
-    if c_ref is not None:
-        from oracle import cmm_oracle as O
-        A16, B16 = W.dequantised(w)
-        c_ref16, _, _ = O.run(A16, B16, w.b, w.d, w.seed, subtract_diag=w.subtract_diag)
+    if c_ref0 is not None:
+        c_q = r["sketch"].c()
+        Aq, Bq = W.dequantised(w)
+        c_refq, _, _ = O.run(Aq, Bq, w.b, w.d, w.seed, subtract_diag=w.subtract_diag)
+        if w0.dtype == "f32":
+            c_ref32 = c_ref0
+        else:
+            w32 = W.make_workload(args.workload, dtype="f32")
+            A32, B32 = W.dequantised(w32)
+            c_ref32, _, _ = O.run(A32, B32, w.b, w.d, w.seed, subtract_diag=w.subtract_diag)
 
         def rel(x, y):
             return max(float(np.linalg.norm(x[t] - y[t]) / np.linalg.norm(y[t])) for t in range(w.d))
-        # total = GPU bf16 vs oracle(f32 values); arithmetic = GPU bf16 vs oracle(bf16 values);
-        # quantisation = oracle(bf16 values) vs oracle(f32 values)
-        res["max_rel_l2_c_vs_f64_oracle_of_f32_operands"] = rel(c16, c_ref)
-        res["max_rel_l2_c_arithmetic"] = rel(c16, c_ref16)
-        res["max_rel_l2_c_quantisation"] = rel(c_ref16, c_ref)
+        res["max_rel_l2_c_arithmetic"] = rel(c_q, c_refq)
+        res["max_rel_l2_c_quantisation"] = rel(c_refq, c_ref32)
+        res["max_rel_l2_c_vs_f64_oracle_of_f32_operands"] = rel(c_q, c_ref32)
     r["sketch"].free()
     return res
 
