@@ -103,6 +103,18 @@ int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out);
 /* Switch the context to another stream; waits for the old one first. */
 int cmm_ctx_set_stream(cmm_ctx* ctx, void* hip_stream);
 
+/* Workspace limit of one product, in bytes (0 restores the default, half of
+ * the device memory).  A product is a sum of m outer products (eq. (1)) and
+ * its sketch is linear in them (Section 2.2), so a product whose workspace
+ * (count sketches of every k, k-split partial spectra, layout tables) would
+ * exceed the limit runs as consecutive k-slabs, each as long as the limit
+ * allows (at least one k), whose float64 sketches are added.  The result
+ * equals the unsplit product's up to float rounding.  Applies to
+ * cmm_sketch_product, _ex, _tables, _sparse and cmm_estimate_nnz; batches,
+ * the autotuner and cmm_find_significant keep whole products.
+ * Errors: CMM_EINVAL for a negative limit or an invalid context. */
+int cmm_ctx_set_workspace_limit(cmm_ctx* ctx, int64_t bytes);
+
 /* Wait for the stream, release every cached buffer and the context. */
 int cmm_ctx_destroy(cmm_ctx* ctx);
 

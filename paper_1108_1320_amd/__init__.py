@@ -47,6 +47,7 @@ _I32P = C.POINTER(_I32)
 _SIGS = {
     "cmm_ctx_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
     "cmm_ctx_set_stream": (C.c_int, [_P, _P]),
+    "cmm_ctx_set_workspace_limit": (C.c_int, [_P, _I64]),
     "cmm_ctx_destroy": (C.c_int, [_P]),
     "cmm_strerror": (C.c_char_p, [C.c_int]),
     "cmm_last_error": (C.c_char_p, [_P]),
@@ -149,6 +150,10 @@ def cmm_ctx_destroy(ctx):
 
 def cmm_ctx_set_stream(ctx, stream):
     _check(load().cmm_ctx_set_stream(ctx, stream), "cmm_ctx_set_stream", ctx)
+
+
+def cmm_ctx_set_workspace_limit(ctx, nbytes: int):
+    _check(load().cmm_ctx_set_workspace_limit(ctx, int(nbytes)), "cmm_ctx_set_workspace_limit", ctx)
 
 
 def cmm_ctx_profile(ctx, enable: bool):
@@ -372,6 +377,11 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_workspace_limit(self, nbytes: int):
+        """Products whose workspace would exceed ``nbytes`` run as k-slabs
+        (0 restores the default, half the device memory)."""
+        cmm_ctx_set_workspace_limit(self.handle, nbytes)
 
     def profile(self, enable: bool):
         cmm_ctx_profile(self.handle, enable)

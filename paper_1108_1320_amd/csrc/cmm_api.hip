@@ -54,6 +54,8 @@ struct cmm_ctx {
   uint32_t* pinned_u32 = nullptr;   // small pinned host scratch
   std::map<TuneKey, TuneEntry> tuning;
   std::string arch;
+  int64_t ws_limit = 0;     // workspace limit of one product in bytes (0: ws_default)
+  int64_t ws_default = 0;   // half the device memory
 };
 
 struct cmm_sketch {
@@ -395,8 +397,12 @@ int enqueue_layout(cmm_ctx* c, const cmm::Geometry& g, cmm::SideDesc side[2],
 // Every kernel of one sketch product, in stream order, on stream `s`: no
 // allocation, no host synchronisation, no host-to-device copy (hash
 // parameters are already at `pdev`), so the sequence can be captured.
+// All kernels of one product on stream `s`.  The float64 sketch goes to
+// `c_out` (the sketch's own when null); `finish` also writes its float32 copy.
 int enqueue_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Geometry& g,
-                    const WsSpec& spec, const WsPtrs& ptr, const uint64_t* pdev, hipStream_t s) {
+                    const WsSpec& spec, const WsPtrs& ptr, const uint64_t* pdev, hipStream_t s,
+                    double* c_out = nullptr, bool finish = true) {
+  double* c64 = c_out ? c_out : sk->c64;
   cmm::SideDesc side[2];
   bind_sides(g, sk, op, spec, ptr, side);
   double2* tw64; float2* tw32;
@@ -415,30 +421,80 @@ int enqueue_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::G
   {
     Scope sc_(c, "ifft");
     CMM_HIP(c, cmm::launch_ifft(g, (float2*)ptr.p[W_PPART], (double2*)ptr.p[W_WORK0],
-                                (double2*)ptr.p[W_WORK1], tw64, sk->c64, s));
+                                (double2*)ptr.p[W_WORK1], tw64, c64, s));
     if (op.flags & CMM_SUBTRACT_DIAG) {
       const int n = (int)sk->n1;
       CMM_HIP(c, cmm::launch_diag(op.dtype, side[0], side[1], g.m, n, (double*)ptr.p[W_PARTIAL],
                                   spec.kch, (double*)ptr.p[W_DIAG], s));
       CMM_HIP(c, cmm::launch_sub_diag(g, sk->hs1, sk->hs2, (int)sk->n1, (int)sk->n3,
-                                      (double*)ptr.p[W_DIAG], n, sk->c64, s));
+                                      (double*)ptr.p[W_DIAG], n, c64, s));
     }
-    CMM_HIP(c, cmm::launch_to_f32(sk->c64, sk->c32, (int64_t)g.d * g.b, s));
+    if (finish) CMM_HIP(c, cmm::launch_to_f32(sk->c64, sk->c32, (int64_t)g.d * g.b, s));
   }
   return CMM_OK;
 }
 
+size_t spec_bytes(const WsSpec& spec) {
+  size_t t = 0;
+  for (int i = 0; i < W_COUNT; ++i) t += spec.count[i] * kElemSize[i];
+  return t;
+}
+
+// Longest k-slab whose workspace stays within the context's limit (all of
+// m when the whole product fits; at least one k).  The workspace grows with
+// the slab length (count sketches, column maxima, k-split partials), so the
+// search is a bisection over the length.
+int64_t slab_length(const cmm_ctx* c, const cmm_sketch* sk, const cmm::Tuning& tu, bool safe,
+                    uint32_t flags) {
+  const int64_t limit = c->ws_limit > 0 ? c->ws_limit : c->ws_default;
+  auto bytes = [&](int64_t mk) {
+    return (int64_t)spec_bytes(ws_spec(make_geometry(sk->b, sk->d, mk, tu), sk->n1, sk->n3, safe, flags));
+  };
+  if (limit <= 0 || bytes(sk->m) <= limit) return sk->m;
+  int64_t lo = 1, hi = sk->m;   // bytes(lo) may exceed the limit: one k is the least
+  while (hi - lo > 1) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (bytes(mid) <= limit) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Operands of the k-slab starting at k0: rows k0.. of both stored operands.
+Operands slab_operands(const Operands& op, int64_t k0) {
+  Operands o = op;
+  if (op.dtype == cmm::kSparseF32) {
+    o.aptr = op.aptr + k0;
+    o.bptr = op.bptr + k0;
+    return o;
+  }
+  const int64_t esz = op.dtype == CMM_F32 ? 4 : (op.dtype == CMM_BF16 ? 2 : 1);
+  o.A = (const char*)op.A + k0 * op.lda * esz;
+  o.B = (const char*)op.B + k0 * op.ldb * esz;
+  return o;
+}
+
 // One product on the context stream with a workspace from the cache.
+// A product whose workspace would exceed the context's limit runs as
+// consecutive k-slabs: the sketch of AB is the sum of the sketches of the
+// slabs' partial products (eq. (1); the sketch is linear), added in float64.
 int run_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Tuning& tu,
                 bool safe_layout, bool* overflowed) {
   hipStream_t s = c->stream;
   const bool async = op.flags & CMM_ASYNC;
-  const cmm::Geometry g = make_geometry(sk->b, sk->d, sk->m, tu);
-  const WsSpec spec = ws_spec(g, sk->n1, sk->n3, safe_layout || async, op.flags);
+  const bool safe = safe_layout || async;
+  const int64_t slab = slab_length(c, sk, tu, safe, op.flags);
+  const cmm::Geometry g = make_geometry(sk->b, sk->d, slab, tu);
+  const WsSpec spec = ws_spec(g, sk->n1, sk->n3, safe, op.flags);
   WsPtrs ptr;
   std::vector<void*> owned;
   uint64_t* pdev = nullptr;
+  double* csum = nullptr;
   int rc = ws_alloc(c, spec, ptr, owned);
+  if (rc == CMM_OK && slab < sk->m) {
+    csum = (double*)dalloc(c, sizeof(double) * sk->d * sk->b);
+    if (!csum) rc = fail(c, CMM_ENOMEM, "workspace allocation failed");
+    else owned.push_back(csum);
+  }
   if (rc == CMM_OK && sk->has_params) {
     pdev = (uint64_t*)dalloc(c, sizeof(uint64_t) * sk->d * 8);
     if (!pdev) rc = fail(c, CMM_ENOMEM, "workspace allocation failed");
@@ -449,7 +505,20 @@ int run_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Tunin
                                   hipMemcpyHostToDevice, s);
     if (e != hipSuccess) rc = fail(c, CMM_EHIP, "parameter upload failed");
   }
-  if (rc == CMM_OK) rc = enqueue_product(c, sk, op, g, spec, ptr, pdev, s);
+  if (rc == CMM_OK && slab >= sk->m) rc = enqueue_product(c, sk, op, g, spec, ptr, pdev, s);
+  // later slabs are shorter or equal: their workspace fits in the first's
+  for (int64_t k0 = 0; rc == CMM_OK && slab < sk->m && k0 < sk->m; k0 += slab) {
+    const cmm::Geometry gk = make_geometry(sk->b, sk->d, std::min(slab, sk->m - k0), tu);
+    const WsSpec sk_spec = ws_spec(gk, sk->n1, sk->n3, safe, op.flags);
+    rc = enqueue_product(c, sk, slab_operands(op, k0), gk, sk_spec, ptr, pdev, s,
+                         k0 == 0 ? sk->c64 : csum, false);
+    if (rc == CMM_OK && k0 > 0 &&
+        cmm::launch_add_f64(sk->c64, csum, (int64_t)sk->d * sk->b, s) != hipSuccess)
+      rc = fail(c, CMM_EHIP, "slab sum launch failed");
+    if (rc == CMM_OK && k0 + slab >= sk->m &&
+        cmm::launch_to_f32(sk->c64, sk->c32, (int64_t)sk->d * sk->b, s) != hipSuccess)
+      rc = fail(c, CMM_EHIP, "float32 copy launch failed");
+  }
   *overflowed = false;
   if (rc == CMM_OK && !async) {
     hipError_t e1 = hipMemcpyAsync(c->pinned_u32, ptr.p[W_OFLOW], sizeof(int32_t),
@@ -930,6 +999,9 @@ int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out) {
     delete c;
     return CMM_ENOMEM;
   }
+  size_t mem_free = 0, mem_total = 0;
+  c->ws_default = hipMemGetInfo(&mem_free, &mem_total) == hipSuccess && mem_total > 0
+                      ? (int64_t)(mem_total / 2) : (int64_t)64 << 30;
   if (cmm::prepare_countsketch() != hipSuccess || cmm::prepare_fft_mac() != hipSuccess ||
       cmm::prepare_sparse() != hipSuccess) {
     hipHostFree(c->pinned_u32);
@@ -938,6 +1010,13 @@ int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out) {
   }
   if (const char* path = std::getenv("CMM_TUNE_CACHE")) load_tuning(c, path, true);
   *out = c;
+  return CMM_OK;
+}
+
+int cmm_ctx_set_workspace_limit(cmm_ctx* ctx, int64_t bytes) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  if (bytes < 0) return fail(ctx, CMM_EINVAL, "workspace limit must be >= 0");
+  ctx->ws_limit = bytes;
   return CMM_OK;
 }
 
