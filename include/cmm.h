@@ -149,7 +149,10 @@ int cmm_sketch_product(cmm_ctx* ctx, const float* A, const float* B, int64_t n,
  * parameters when non-NULL.  `flags` combines CMM_SUBTRACT_DIAG (requires
  * n1 == n3; subtracts s1(i)s2(i)(AB)_ii from bucket (h1(i)+h2(i)) mod b,
  * giving the sketch of the product with a zero diagonal, Section 3.2) and
- * CMM_ASYNC. */
+ * CMM_ASYNC.  Sizes: n1, n3 <= 65535 (CMM_EUNSUPPORTED above; rows of up to
+ * 24576 elements are staged in LDS, longer ones are read from global
+ * memory), m <= 2^30, b a power of two in [16, 2^20], 1 <= d <= 63
+ * (CMM_EINVAL otherwise). */
 int cmm_sketch_product_ex(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
                           int64_t n1, int64_t m, int64_t n3, int32_t dtype,
                           const float* scaleA, const float* scaleB, int64_t b, int32_t d,
@@ -177,7 +180,8 @@ int cmm_sketch_product_tables(cmm_ctx* ctx, const void* A, int64_t lda, const vo
  * from the staged row on).  Offsets and index ranges are checked on the
  * device first (CMM_EINVAL); repeated indices are not detected.  An operand
  * without entries may pass NULL index and value arrays.  flags:
- * CMM_SUBTRACT_DIAG (n1 == n3), CMM_ASYNC. */
+ * CMM_SUBTRACT_DIAG (n1 == n3), CMM_ASYNC.  n1, n3 <= 24576 (every row is
+ * staged in LDS; CMM_EUNSUPPORTED above). */
 int cmm_sketch_product_sparse(cmm_ctx* ctx, const int64_t* a_ptr, const int32_t* a_idx,
                               const float* a_val, const int64_t* b_ptr, const int32_t* b_idx,
                               const float* b_val, int64_t n1, int64_t m, int64_t n3, int64_t b,

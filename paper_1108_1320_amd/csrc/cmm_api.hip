@@ -331,8 +331,8 @@ int check_operands(cmm_ctx* c, const void* A, int64_t lda, const void* B, int64_
   if (dtype < CMM_F32 || dtype > CMM_FP8_E4M3) return fail(c, CMM_EINVAL, "unknown dtype");
   if (!is_pow2(b) || b < 16 || b > (1 << 20)) return fail(c, CMM_EINVAL, "b must be a power of two in [16, 2^20]");
   if (d < 1 || d > 63) return fail(c, CMM_EINVAL, "d must be in [1, 63]");
-  if (std::max(n1, n3) * (int64_t)sizeof(float) > 96 * 1024)
-    return fail(c, CMM_EUNSUPPORTED, "hashed dimension above 24576 (count-sketch row staging)");
+  if (std::max(n1, n3) > cmm::kMaxHashedDim)
+    return fail(c, CMM_EUNSUPPORTED, "hashed dimension above 65535");
   return CMM_OK;
 }
 
@@ -1003,7 +1003,7 @@ int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out) {
   c->ws_default = hipMemGetInfo(&mem_free, &mem_total) == hipSuccess && mem_total > 0
                       ? (int64_t)(mem_total / 2) : (int64_t)64 << 30;
   if (cmm::prepare_countsketch() != hipSuccess || cmm::prepare_fft_mac() != hipSuccess ||
-      cmm::prepare_sparse() != hipSuccess) {
+      cmm::prepare_sparse() != hipSuccess || cmm::prepare_decode() != hipSuccess) {
     hipHostFree(c->pinned_u32);
     delete c;
     return CMM_EHIP;
@@ -1210,7 +1210,6 @@ int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int6
   Work w(c);
   if (mode == CMM_TOPK_PER_COLUMN) {
     if (K > sk->n1) return fail(c, CMM_EINVAL, "K larger than a column");
-    if (sk->n1 * 4 > 64 * 1024) return fail(c, CMM_EUNSUPPORTED, "per-column top-K needs n1 <= 16384");
     const size_t tot = (size_t)K * sk->n3;
     int64_t* oi = w.get<int64_t>(tot);
     float* ov = w.get<float>(tot);
@@ -1714,6 +1713,8 @@ int cmm_sketch_product_sparse(cmm_ctx* ctx, const int64_t* a_ptr, const int32_t*
   *out = nullptr;
   if (!a_ptr || !b_ptr) return fail(ctx, CMM_EINVAL, "sparse offsets must be device pointers");
   if (m <= 0 || m > (1 << 30)) return fail(ctx, CMM_EINVAL, "m out of range");
+  if (std::max(n1, n3) > cmm::kMaxStagedDim)
+    return fail(ctx, CMM_EUNSUPPORTED, "sparse operands: hashed dimension above 24576 (rows are staged in LDS)");
   CMM_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   {

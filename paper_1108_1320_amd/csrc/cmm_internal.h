@@ -91,6 +91,15 @@ __host__ __device__ __forceinline__ uint32_t pad_entry(int w, int G, int r) {
 }
 
 constexpr int kMaxLog2C = 13;          // FFT row length C <= 8192
+// Hashed dimensions n1, n3: rows up to kMaxStagedDim floats are staged in LDS
+// by the count-sketch kernel (sparse operands always are); dense rows up to
+// kMaxHashedDim are read from global memory instead.  n1 * n3 < 2^32 keeps
+// every top-K histogram count inside uint32.
+constexpr int kMaxStagedDim = 24576;
+constexpr int kMaxHashedDim = 65535;
+// per-column top-K keeps a column's keys in LDS up to this many rows and
+// recomputes them each round above it
+constexpr int kMaxColumnKeys = 40704;   // 159 KB of keys + the static shared words
 constexpr int kTopkCap = 4096;         // candidates sorted by the final top-K pass
 constexpr int kMaxKPerBlock = 128;     // k per FFT block (float32 partial sums)
 
@@ -158,6 +167,7 @@ hipError_t launch_count(const Geometry& g, SideDesc& sd, hipStream_t s);
 hipError_t launch_layout(const Geometry& g, SideDesc& sd, int32_t* overflow, hipStream_t s);
 hipError_t prepare_countsketch();
 hipError_t prepare_fft_mac();
+hipError_t prepare_decode();
 hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStream_t s);
 hipError_t launch_fft_mac(const Geometry& g, const SideDesc& a, const SideDesc& bside,
                           const float2* tw32, float2* Ppart, hipStream_t s);

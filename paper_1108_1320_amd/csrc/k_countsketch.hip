@@ -5,7 +5,9 @@
 // The stored operands are k-major (Section 2.2's single-pass order), so the
 // vector to sketch for a given k is one contiguous row of n elements.  A
 // block stages that row in LDS (dequantising bf16 / fp8 and applying the
-// per-position scale), then, for every repetition, writes the row's sketch
+// per-position scale; rows longer than the 24576 floats LDS staging holds
+// are read element by element from global memory, where they stay in L2),
+// then, for every repetition, writes the row's sketch
 // in the bucket layout of the FFT kernel: position p holds the signed sum of
 // the row entries of the bucket placed there.  Members of a bucket are summed
 // in increasing index order, so the result does not depend on scheduling.
@@ -49,8 +51,9 @@ template <> struct Elem<2> {      // fp8 e4m3fn bits
 // like the integers), one barrier per row.
 constexpr int kCsThreads = 512;
 
-template <int DT>
+template <int DT, bool STAGED>
 __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, int m, int W, int kblock) {
+  static_assert(STAGED || DT != kSparseF32, "sparse rows are always staged");
   extern __shared__ float row[];
   __shared__ uint32_t smax[2][64];
   typedef Elem<DT == kSparseF32 ? 0 : DT> E;
@@ -64,7 +67,15 @@ __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, 
   if (tid < 128) smax[tid >> 6][tid & 63] = 0u;
   int par = 0;
   for (int k = k0; k < k1; ++k, par ^= 1) {
-    if constexpr (DT == kSparseF32) {
+    const S* xr = DT == kSparseF32 ? X : X + (int64_t)k * sd.ld;
+    // value of row element x (dequantised and scaled)
+    auto val = [&](int x) -> float {
+      if constexpr (STAGED) return row[x];
+      else return E::one(xr[x]) * (sd.scale ? sd.scale[x] : 1.0f);
+    };
+    if constexpr (!STAGED) {
+      // nothing to stage
+    } else if constexpr (DT == kSparseF32) {
       // sparse row: zero the staged row, then scatter the row's entries
       for (int x = tid; x < n; x += kCsThreads) row[x] = 0.0f;
       __syncthreads();
@@ -72,7 +83,6 @@ __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, 
       for (int64_t e = sd.sptr[k] + tid; e < e1; e += kCsThreads) row[sd.sidx[e]] = X[e];
       __syncthreads();
     } else {
-    const S* xr = X + (int64_t)k * sd.ld;
     // the row's first `head` elements are staged one by one, the body four at
     // a time from an address aligned to four elements, then the tail
     const int head = min(n, (int)((4 - ((uintptr_t)xr / sizeof(S)) % 4) % 4));
@@ -120,7 +130,7 @@ __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, 
           const uint32_t e = ev[q];
           float x = 0.0f;
           if (e != CMM_PAD_TAB) {
-            x = row[e & CMM_TAB_IDX];
+            x = val((int)(e & CMM_TAB_IDX));
             if (e & CMM_TAB_NEG) x = -x;
             if (e & CMM_TAB_MORE) {
               const int64_t tp = (int64_t)t * sd.Lrow + p + q;
@@ -129,7 +139,7 @@ __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, 
               const int32_t* hs = sd.hs + (int64_t)t * n;
               for (int a = 1; a < c; ++a) {
                 const int xm = mem[a];
-                const float y = row[xm];
+                const float y = val(xm);
                 x += (hs[xm] & 1) ? -y : y;
               }
             }
@@ -154,15 +164,16 @@ hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStr
   int kblock = (int)((int64_t)g.m / std::max(1, g.cs_blocks));
   if (kblock < 1) kblock = 1;
   const int blocks = (g.m + kblock - 1) / kblock;
-  const size_t lds = (size_t)sd.n * sizeof(float);
-  if (dtype == 0)
-    hipLaunchKernelGGL(k_countsketch<0>, dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock);
-  else if (dtype == 1)
-    hipLaunchKernelGGL(k_countsketch<1>, dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock);
-  else if (dtype == 2)
-    hipLaunchKernelGGL(k_countsketch<2>, dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock);
-  else
-    hipLaunchKernelGGL(k_countsketch<kSparseF32>, dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock);
+  const bool staged = sd.n <= kMaxStagedDim;
+  if (!staged && dtype == kSparseF32) return hipErrorInvalidValue;
+  const size_t lds = staged ? (size_t)sd.n * sizeof(float) : 0;
+#define CMM_CS(DT, ST) \
+  hipLaunchKernelGGL((k_countsketch<DT, ST>), dim3(blocks), dim3(kCsThreads), lds, s, sd, g.d, g.m, g.W, kblock)
+  if (dtype == 0) { if (staged) CMM_CS(0, true); else CMM_CS(0, false); }
+  else if (dtype == 1) { if (staged) CMM_CS(1, true); else CMM_CS(1, false); }
+  else if (dtype == 2) { if (staged) CMM_CS(2, true); else CMM_CS(2, false); }
+  else CMM_CS(kSparseF32, true);
+#undef CMM_CS
   return hipGetLastError();
 }
 
@@ -170,10 +181,10 @@ hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStr
 // row of up to 24576 floats needs (done once per context, outside any graph
 // capture).
 hipError_t prepare_countsketch() {
-  const void* fns[] = {reinterpret_cast<const void*>(&k_countsketch<0>),
-                       reinterpret_cast<const void*>(&k_countsketch<1>),
-                       reinterpret_cast<const void*>(&k_countsketch<2>),
-                       reinterpret_cast<const void*>(&k_countsketch<kSparseF32>)};
+  const void* fns[] = {reinterpret_cast<const void*>(&k_countsketch<0, true>),
+                       reinterpret_cast<const void*>(&k_countsketch<1, true>),
+                       reinterpret_cast<const void*>(&k_countsketch<2, true>),
+                       reinterpret_cast<const void*>(&k_countsketch<kSparseF32, true>)};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
     if (e != hipSuccess) return e;

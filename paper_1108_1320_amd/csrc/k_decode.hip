@@ -264,7 +264,11 @@ __global__ __launch_bounds__(1024) void k_topk_final(const TopkCand* __restrict_
 
 // ---------------------------------------------------------------- per column
 
-template <int D>
+// One block per column j; K rounds, each picking the best (|estimate|, then
+// smaller i) strictly below the previous pick.  STORE keeps the column's
+// keys in LDS (n1 <= kMaxColumnKeys); otherwise every round decodes the
+// column again.
+template <int D, bool STORE>
 __global__ __launch_bounds__(256) void k_topk_column(DecodeDesc dd, int K, int64_t* __restrict__ oi,
                                                      float* __restrict__ ov) {
   extern __shared__ uint32_t keys[];
@@ -273,18 +277,22 @@ __global__ __launch_bounds__(256) void k_topk_column(DecodeDesc dd, int K, int64
   const int j = blockIdx.x;
   HashVec<D> h2;
   load_hash<D>(h2, dd.hs2, dd.n3, j, dd.d);
-  for (int i = tid; i < dd.n1; i += 256) {
+  auto key = [&](int i) -> uint32_t {
     HashVec<D> h1;
     load_hash<D>(h1, dd.hs1, dd.n1, i, dd.d);
-    keys[i] = __float_as_uint(fabsf(estimate<D>(dd, h1.v, h2.v, dd.d)));
+    return __float_as_uint(fabsf(estimate<D>(dd, h1.v, h2.v, dd.d)));
+  };
+  if constexpr (STORE) {
+    for (int i = tid; i < dd.n1; i += 256) keys[i] = key(i);
+    __syncthreads();
   }
-  __syncthreads();
   unsigned long long last = ~0ull;
   for (int r = 0; r < K; ++r) {
     // packed (key, ~i): larger is better; pick the best strictly below `last`
     unsigned long long best = 0ull;
     for (int i = tid; i < dd.n1; i += 256) {
-      const unsigned long long p = ((unsigned long long)keys[i] << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)i);
+      const uint32_t kv = STORE ? keys[i] : key(i);
+      const unsigned long long p = ((unsigned long long)kv << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)i);
       if (p < last && p > best) best = p;
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -378,11 +386,28 @@ hipError_t launch_topk_final(const TopkCand* cand, const uint32_t* count, int ca
 }
 
 hipError_t launch_topk_column(const DecodeDesc& dd, int K, int64_t* oi, float* ov, hipStream_t s) {
-  const size_t lds = (size_t)dd.n1 * sizeof(uint32_t);
-#define CMM_K(DV) hipLaunchKernelGGL(k_topk_column<DV>, dim3(dd.n3), dim3(256), lds, s, dd, K, oi, ov)
+  const bool store = dd.n1 <= kMaxColumnKeys;
+  const size_t lds = store ? (size_t)dd.n1 * sizeof(uint32_t) : 0;
+#define CMM_K(DV)                                                                              \
+  if (store) hipLaunchKernelGGL((k_topk_column<DV, true>), dim3(dd.n3), dim3(256), lds, s, dd, K, oi, ov); \
+  else hipLaunchKernelGGL((k_topk_column<DV, false>), dim3(dd.n3), dim3(256), 0, s, dd, K, oi, ov)
   CMM_DISPATCH_D(dd.d, CMM_K)
 #undef CMM_K
   return hipGetLastError();
+}
+
+// Raise the dynamic LDS limit of the stored per-column top-K to its 160 KB
+// of keys (done once per context, outside any graph capture).
+hipError_t prepare_decode() {
+#define CMM_P(DV)                                                                          \
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_topk_column<DV, true>),          \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, kMaxColumnKeys * 4);  \
+  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  CMM_P(0) CMM_P(1) CMM_P(2) CMM_P(3) CMM_P(4) CMM_P(5) CMM_P(6) CMM_P(7) CMM_P(8)
+  CMM_P(9) CMM_P(10) CMM_P(11) CMM_P(12) CMM_P(13) CMM_P(14) CMM_P(15)
+#undef CMM_P
+  return hipSuccess;
 }
 
 }  // namespace cmm
