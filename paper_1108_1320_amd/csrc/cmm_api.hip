@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <tuple>
 #include <string>
@@ -52,6 +53,7 @@ struct cmm_ctx {
   std::vector<Pending> pending;
   std::map<std::string, std::pair<double, int64_t>> prof_acc;
   uint32_t* pinned_u32 = nullptr;   // small pinned host scratch
+  char* pinned = nullptr;           // pinned staging of small downloads (kPinnedBytes)
   std::map<TuneKey, TuneEntry> tuning;
   std::string arch;
   int64_t ws_limit = 0;     // workspace limit of one product in bytes (0: ws_default)
@@ -80,12 +82,26 @@ int fail(cmm_ctx* c, int code, const std::string& msg) {
   return code;
 }
 
+constexpr size_t kPinnedBytes = 256 * 1024;
+
 #define CMM_HIP(ctx, expr)                                                          \
   do {                                                                              \
     hipError_t e__ = (expr);                                                        \
     if (e__ != hipSuccess)                                                          \
       return fail((ctx), CMM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e__)); \
   } while (0)
+
+struct Download {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+
+// Device-to-host copies on stream `s`, then a wait.  A pageable destination
+// makes the runtime stage the copy through a blit kernel; copies that fit
+// together go through the context's pinned buffer instead (plain DMA) and
+// are moved to their destinations on the host.
+int download(cmm_ctx* c, hipStream_t s, std::initializer_list<Download> list);
 
 bool valid_ctx(const cmm_ctx* c) { return c && c->magic == kCtxMagic; }
 bool valid_sketch(const cmm_sketch* s) { return s && s->magic == kSketchMagic && valid_ctx(s->ctx); }
@@ -397,6 +413,29 @@ int enqueue_layout(cmm_ctx* c, const cmm::Geometry& g, cmm::SideDesc side[2],
 // Every kernel of one sketch product, in stream order, on stream `s`: no
 // allocation, no host synchronisation, no host-to-device copy (hash
 // parameters are already at `pdev`), so the sequence can be captured.
+int download(cmm_ctx* c, hipStream_t s, std::initializer_list<Download> list) {
+  size_t total = 0;
+  for (const Download& x : list) total += (x.bytes + 255) & ~(size_t)255;
+  const bool staged = c->pinned && total <= kPinnedBytes;
+  size_t off = 0;
+  for (const Download& x : list) {
+    if (x.bytes == 0) continue;
+    void* to = staged ? (void*)(c->pinned + off) : x.dst;
+    CMM_HIP(c, hipMemcpyAsync(to, x.src, x.bytes, hipMemcpyDeviceToHost, s));
+    off += (x.bytes + 255) & ~(size_t)255;
+  }
+  CMM_HIP(c, hipStreamSynchronize(s));
+  if (staged) {
+    off = 0;
+    for (const Download& x : list) {
+      if (x.bytes == 0) continue;
+      std::memcpy(x.dst, c->pinned + off, x.bytes);
+      off += (x.bytes + 255) & ~(size_t)255;
+    }
+  }
+  return CMM_OK;
+}
+
 // All kernels of one product on stream `s`.  The float64 sketch goes to
 // `c_out` (the sketch's own when null); `finish` also writes its float32 copy.
 int enqueue_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Geometry& g,
@@ -995,7 +1034,9 @@ int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out) {
   cmm_ctx* c = new cmm_ctx();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
-  if (hipHostMalloc((void**)&c->pinned_u32, 64 * sizeof(uint32_t)) != hipSuccess) {
+  if (hipHostMalloc((void**)&c->pinned_u32, 64 * sizeof(uint32_t)) != hipSuccess ||
+      hipHostMalloc((void**)&c->pinned, kPinnedBytes) != hipSuccess) {
+    if (c->pinned_u32) hipHostFree(c->pinned_u32);
     delete c;
     return CMM_ENOMEM;
   }
@@ -1005,6 +1046,7 @@ int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out) {
   if (cmm::prepare_countsketch() != hipSuccess || cmm::prepare_fft_mac() != hipSuccess ||
       cmm::prepare_sparse() != hipSuccess || cmm::prepare_decode() != hipSuccess) {
     hipHostFree(c->pinned_u32);
+    hipHostFree(c->pinned);
     delete c;
     return CMM_EHIP;
   }
@@ -1035,6 +1077,7 @@ int cmm_ctx_destroy(cmm_ctx* ctx) {
   for (auto& kv : ctx->sizes) hipFree(kv.first);
   for (auto& kv : ctx->twiddles) { hipFree(kv.second.first); hipFree(kv.second.second); }
   if (ctx->pinned_u32) hipHostFree(ctx->pinned_u32);
+  if (ctx->pinned) hipHostFree(ctx->pinned);
   ctx->magic = kDeadMagic;
   delete ctx;
   return CMM_OK;
@@ -1171,13 +1214,13 @@ int cmm_estimate(const cmm_sketch* sk, int64_t i, int64_t j, double* out) {
   std::vector<double> x((size_t)sk->d);
   for (int t = 0; t < sk->d; ++t) {
     int32_t a = 0, b2 = 0;
-    CMM_HIP(c, hipMemcpyAsync(&a, sk->hs1 + (size_t)t * sk->n1 + i, 4, hipMemcpyDeviceToHost, c->stream));
-    CMM_HIP(c, hipMemcpyAsync(&b2, sk->hs2 + (size_t)t * sk->n3 + j, 4, hipMemcpyDeviceToHost, c->stream));
-    CMM_HIP(c, hipStreamSynchronize(c->stream));
+    int rc = download(c, c->stream, {{&a, sk->hs1 + (size_t)t * sk->n1 + i, 4},
+                                     {&b2, sk->hs2 + (size_t)t * sk->n3 + j, 4}});
+    if (rc) return rc;
     const int64_t u = ((int64_t)(a >> 1) + (b2 >> 1)) & (sk->b - 1);
     double v = 0.0;
-    CMM_HIP(c, hipMemcpyAsync(&v, sk->c64 + (size_t)t * sk->b + u, 8, hipMemcpyDeviceToHost, c->stream));
-    CMM_HIP(c, hipStreamSynchronize(c->stream));
+    rc = download(c, c->stream, {{&v, sk->c64 + (size_t)t * sk->b + u, 8}});
+    if (rc) return rc;
     x[t] = ((a ^ b2) & 1) ? -v : v;
   }
   std::sort(x.begin(), x.end());
@@ -1218,9 +1261,8 @@ int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int6
       Scope sc_(c, "decode");
       CMM_HIP(c, cmm::launch_topk_column(dd, K, oi, ov, s));
     }
-    CMM_HIP(c, hipMemcpyAsync(out_i, oi, sizeof(int64_t) * tot, hipMemcpyDeviceToHost, s));
-    CMM_HIP(c, hipMemcpyAsync(out_val, ov, sizeof(float) * tot, hipMemcpyDeviceToHost, s));
-    CMM_HIP(c, hipStreamSynchronize(s));
+    const int rc = download(c, s, {{out_i, oi, sizeof(int64_t) * tot}, {out_val, ov, sizeof(float) * tot}});
+    if (rc) return rc;
     for (int64_t jj = 0; jj < sk->n3; ++jj)
       for (int r = 0; r < K; ++r) out_j[jj * K + r] = jj;
     return CMM_OK;
@@ -1255,8 +1297,7 @@ int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int6
     if (tiles >= 64) {
       CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
       CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 16, 0, 32, 19, 0xFFF, hist, 0, nullptr, nullptr, 0, s));
-      CMM_HIP(c, hipMemcpyAsync(h.data(), hist, 4096 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-      CMM_HIP(c, hipStreamSynchronize(s));
+      { const int rc_ = download(c, s, {{h.data(), hist, 4096 * sizeof(uint32_t)}}); if (rc_) return rc_; }
       int64_t sampled = 0;
       for (uint32_t x : h) sampled += x;
       int b0 = -1;
@@ -1273,8 +1314,7 @@ int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int6
         CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
         CMM_HIP(c, cmm::launch_fill_i32((int32_t*)count, 2, 0, s));
         CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 1, 0, 32, 19, 0xFFF, hist, T0, wide, count, kWide, s));
-        CMM_HIP(c, hipMemcpyAsync(h.data(), hist, 4096 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        CMM_HIP(c, hipStreamSynchronize(s));
+        { const int rc_ = download(c, s, {{h.data(), hist, 4096 * sizeof(uint32_t)}}); if (rc_) return rc_; }
         // h counts only keys >= T0 (bins b0 and up): exact there
         int64_t n0 = 0;
         for (int q = b0; q < 4096; ++q) n0 += h[q];
@@ -1308,8 +1348,7 @@ int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int6
         CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
         CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 1, prefix, pshift, dshift[level], dmask[level], hist,
                                          0, nullptr, nullptr, 0, s));
-        CMM_HIP(c, hipMemcpyAsync(h.data(), hist, 4096 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-        CMM_HIP(c, hipStreamSynchronize(s));
+        { const int rc_ = download(c, s, {{h.data(), hist, 4096 * sizeof(uint32_t)}}); if (rc_) return rc_; }
         int64_t cum = 0;
         int bin = -1;
         for (int q = (int)dmask[level]; q >= 0; --q) {
@@ -1330,11 +1369,8 @@ int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int6
       CMM_HIP(c, cmm::launch_topk_final(cand, count, cmm::kTopkCap, K, (int)sk->n3, oi, oj, ov, s));
     }
   }
-  CMM_HIP(c, hipMemcpyAsync(out_i, oi, sizeof(int64_t) * K, hipMemcpyDeviceToHost, s));
-  CMM_HIP(c, hipMemcpyAsync(out_j, oj, sizeof(int64_t) * K, hipMemcpyDeviceToHost, s));
-  CMM_HIP(c, hipMemcpyAsync(out_val, ov, sizeof(float) * K, hipMemcpyDeviceToHost, s));
-  CMM_HIP(c, hipStreamSynchronize(s));
-  return CMM_OK;
+  return download(c, s, {{out_i, oi, sizeof(int64_t) * K}, {out_j, oj, sizeof(int64_t) * K},
+                         {out_val, ov, sizeof(float) * K}});
 }
 
 int cmm_batch_create(cmm_ctx* ctx, const cmm_problem* probs, int32_t count, uint32_t flags,
