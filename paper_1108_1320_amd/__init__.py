@@ -378,6 +378,12 @@ class Context:
         except Exception:
             pass
 
+    def set_stream(self, stream=None):
+        """Order the context's work on ``stream`` (a torch.cuda.Stream; None:
+        torch's current stream) from now on; waits for the old stream first."""
+        s = C.c_void_p(stream.cuda_stream) if stream is not None else _current_stream()
+        cmm_ctx_set_stream(self.handle, s)
+
     def set_workspace_limit(self, nbytes: int):
         """Products whose workspace would exceed ``nbytes`` run as k-slabs
         (0 restores the default, half the device memory)."""
