@@ -282,9 +282,62 @@ __global__ __launch_bounds__(256) void k_topk_column(DecodeDesc dd, int K, int64
     load_hash<D>(h1, dd.hs1, dd.n1, i, dd.d);
     return __float_as_uint(fabsf(estimate<D>(dd, h1.v, h2.v, dd.d)));
   };
-  if constexpr (STORE) {
-    for (int i = tid; i < dd.n1; i += 256) keys[i] = key(i);
+  // the best key strictly below `last` over keys[0 .. cnt) (block-wide)
+  auto best_below = [&](int cnt, unsigned long long last) -> unsigned long long {
+    unsigned long long best = 0ull;
+    for (int i = tid; i < cnt; i += 256) {
+      const unsigned long long p = ((unsigned long long)keys[i] << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)i);
+      if (p < last && p > best) best = p;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long o = __shfl_xor(best, off, 64);
+      best = o > best ? o : best;
+    }
+    if (lane == 0) wbest[wv] = best;
     __syncthreads();
+    best = wbest[0];
+    for (int q = 1; q < 4; ++q) best = wbest[q] > best ? wbest[q] : best;
+    __syncthreads();
+    return best;
+  };
+  if constexpr (STORE) {
+    bool exact = true;
+    if constexpr (D > 0) {
+      if (dd.n1 >= 1024) {
+        // threshold from every 16th row: the r-th largest sampled key with
+        // r = ceil(K/16) + 2 leaves about 16 r >= K + 32 rows above it; the
+        // full pass then stops decoding a row as soon as its median cannot
+        // reach the threshold (estimate_above), and keeps key 0 for it
+        const int ns = (dd.n1 + 15) / 16;
+        for (int q = tid; q < ns; q += 256) keys[q] = key(16 * q);
+        __syncthreads();
+        const int rr = min(ns, (K + 15) / 16 + 2);
+        unsigned long long lastp = ~0ull;
+        for (int r = 0; r < rr; ++r) lastp = best_below(ns, lastp);
+        const uint32_t T = (uint32_t)(lastp >> 32);
+        __shared__ int survivors;
+        if (tid == 0) survivors = 0;
+        __syncthreads();
+        int mine = 0;
+        for (int i = tid; i < dd.n1; i += 256) {
+          HashVec<D> h1;
+          load_hash<D>(h1, dd.hs1, dd.n1, i, dd.d);
+          const float e = estimate_above<D>(dd, h1.v, h2.v, __uint_as_float(T));
+          const bool keep = e == e && __float_as_uint(fabsf(e)) >= T;
+          keys[i] = keep ? __float_as_uint(fabsf(e)) : 0u;
+          mine += keep;
+        }
+        atomicAdd(&survivors, mine);
+        __syncthreads();
+        // exact when at least K rows reach T: every row left at key 0 lies
+        // below all of them
+        exact = survivors < K;
+      }
+    }
+    if (exact) {
+      for (int i = tid; i < dd.n1; i += 256) keys[i] = key(i);
+      __syncthreads();
+    }
   }
   unsigned long long last = ~0ull;
   for (int r = 0; r < K; ++r) {

@@ -265,19 +265,31 @@ def test_topk_parity_large_domain(cmm, ctx, case):
     assert np.all(lin[1:][same] > lin[:-1][same])
 
 
-def test_topk_per_column_parity(cmm, ctx):
-    _say("case: top-K per column")
-    At, B = _rand_problem(500, 120, 64, 17)
-    b, d, K = 4096, 3, 6
+# (n1, m, n3, b, d, K): 500 rows decode every row; from 1024 rows a 1-in-16
+# sample sets a threshold and rows that cannot reach it stop early (d = 5,
+# 7; K = 1000 of 1024 leaves too few rows above it, so the exact pass runs)
+COLUMN_CASES = [
+    (500, 120, 64, 4096, 3, 6),
+    (3000, 80, 40, 8192, 5, 40),
+    (2048, 64, 24, 8192, 7, 300),
+    (1024, 40, 8, 4096, 5, 1000),
+]
+
+
+@pytest.mark.parametrize("case", COLUMN_CASES, ids=[f"{c[0]}x{c[2]}_d{c[4]}_K{c[5]}" for c in COLUMN_CASES])
+def test_topk_per_column_parity(cmm, ctx, case):
+    n1, m, n3, b, d, K = case
+    _say(f"case: top-K per column {case}")
+    At, B = _rand_problem(n1, m, n3, 17 + n1)
     sk = cmm.sketch_product(ctx, _dev(At), _dev(B), b, d, seed=41)
     c_ref, tabs, _ = _oracle_c(At, B, b, d, 41)
     oi, oj, ov = sk.topk(K, "column")
-    C = O.decode_all(c_ref, tabs, 500, 64)
+    C = O.decode_all(c_ref, tabs, n1, n3)
     delta = 2 * (np.abs(sk.c().astype(np.float32).astype(np.float64) - c_ref).max() + 1e-6 * np.abs(c_ref).max())
-    for jj in range(64):
+    for jj in range(n3):
         rows = oi[jj * K:(jj + 1) * K]
         assert np.all(oj[jj * K:(jj + 1) * K] == jj)
-        _check_topk(rows, ov[jj * K:(jj + 1) * K], C[:, jj], np.arange(500), K, delta)
+        _check_topk(rows, ov[jj * K:(jj + 1) * K], C[:, jj], np.arange(n1), K, delta)
 
 
 # --------------------------------------------------------------- precision
