@@ -37,6 +37,10 @@
  * - b must be a power of two in [16, 2^20]; 1 <= d <= 63.
  * - Objects are library-owned: free sketches with cmm_sketch_free() before
  *   destroying their context with cmm_ctx_destroy().
+ * - A context and its sketches are used by one host thread at a time (the
+ *   context holds a buffer cache and small pinned staging buffers); threads
+ *   that work concurrently each create their own context, which may share
+ *   the device and run on their own streams.
  */
 #ifndef CMM_H
 #define CMM_H
