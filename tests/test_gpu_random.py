@@ -1,0 +1,93 @@
+"""Seeded random sweep of GPU parity through the C ABI: shapes, b, d,
+operand formats, strides, the diagonal flag and stored tunings drawn at
+random (a fixed seed, so every run checks the same cases), each sketch
+against the float64 oracle on the values the GPU multiplies, and the top-K
+estimates against oracle decodes."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cmm_oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-5
+N_CASES = 120
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx(cmm):
+    c = cmm.Context(0)
+    yield c
+    c.close()
+
+
+def _cases():
+    g = np.random.default_rng(20261203)
+    out = []
+    for q in range(N_CASES):
+        n1 = int(np.exp(g.uniform(0, np.log(3000))))
+        square = g.random() < 0.3
+        n3 = n1 if square else int(np.exp(g.uniform(0, np.log(3000))))
+        m = int(np.exp(g.uniform(0, np.log(300))))
+        b = 1 << int(g.integers(4, 19))
+        d = int(g.integers(1, 10))
+        dtype = ["f32", "bf16", "fp8"][int(g.integers(0, 3))]
+        diag = bool(square and g.random() < 0.5)
+        pad1, pad3 = int(g.integers(0, 2) * g.integers(1, 40)), int(g.integers(0, 2) * g.integers(1, 40))
+        tune = None
+        if g.random() < 0.3:
+            tune = (int(g.integers(9, 14)), int([16, 32, 64, 128][int(g.integers(0, 4))]),
+                    int([1, 64, 512, 4096][int(g.integers(0, 4))]))
+        out.append((q, n1, m, n3, b, d, dtype, diag, pad1, pad3, tune, int(g.integers(0, 1 << 30))))
+    return out
+
+
+@pytest.mark.parametrize("case", _cases(), ids=lambda c: f"r{c[0]}")
+def test_random_parity(cmm, ctx, case):
+    import torch
+    q, n1, m, n3, b, d, dtype, diag, pad1, pad3, tune, seed = case
+    _say(f"case: random {case}")
+    g = np.random.default_rng(seed)
+    At = g.standard_normal((m, n1))
+    B = At.copy() if diag else g.standard_normal((m, n3))
+    sa, scA, Aq = W._encode(At, dtype)
+    sb, scB, Bq = W._encode(B, dtype)
+    # operands inside wider rows (leading dimension n + pad)
+    def dev(x, pad):
+        big = np.zeros((x.shape[0], x.shape[1] + pad), x.dtype)
+        big[:, :x.shape[1]] = x
+        return torch.from_numpy(big).cuda()[:, :x.shape[1]]
+    dA, dB = dev(sa, pad1), dev(sb, pad3)
+    sA = torch.from_numpy(scA).cuda() if scA is not None else None
+    sB = torch.from_numpy(scB).cuda() if scB is not None else None
+    if tune is not None:
+        ctx.set_tuning(n1, m, n3, b, d, dtype, tune)
+    sk = cmm.sketch_product(ctx, dA, dB, b, d, seed=seed, dtype=dtype, scaleA=sA, scaleB=sB,
+                            subtract_diag=diag)
+    c = sk.c()
+    c_ref, tabs, _ = O.run(Aq.T, Bq, b, d, seed, subtract_diag=diag)
+    scale = np.abs(c_ref).max()
+    for t in range(d):
+        nrm = np.linalg.norm(c_ref[t])
+        if nrm <= 1e-12 * max(scale, 1e-300):
+            assert np.abs(c[t]).max() <= 1e-6 * max(scale, 1.0)
+        else:
+            assert np.linalg.norm(c[t] - c_ref[t]) / nrm <= REL_TOL, (t, np.linalg.norm(c[t] - c_ref[t]) / nrm)
+    # returned top-K values are the estimates at the returned positions
+    mode = "upper" if diag and n1 > 1 else "all"
+    dom = n1 * (n1 - 1) // 2 if mode == "upper" else n1 * n3
+    K = int(min(8, dom))
+    if K >= 1:
+        oi, oj, ov = sk.topk(K, mode)
+        if mode == "upper":
+            assert np.all(oi < oj)
+        err = np.abs(c.astype(np.float64) - c_ref).max()
+        assert np.abs(ov - O.decode(c_ref, tabs, oi, oj)).max() <= err + 1e-6 * max(scale, 1e-30)
