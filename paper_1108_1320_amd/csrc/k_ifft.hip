@@ -11,6 +11,8 @@
 #include "cmm_internal.h"
 #include "cmm_dft.h"
 
+#include <algorithm>
+
 namespace cmm {
 
 // Psum[t][f1][f2] = sum over ks of Ppart[t][ks][f1][f2]
@@ -113,11 +115,14 @@ hipError_t launch_ifft(const Geometry& g, const float2* Ppart, double2* work0, d
   for (int p = 0; p < passes; ++p) {
     const int rs = (p == 0 && rem) ? (1 << rem) : 16;
     const int64_t nthreads = (int64_t)g.d * (g.b / rs);
+    // one wave per block: d * b / 16 butterflies are only a few hundred
+    // waves, which then spread over every CU instead of a quarter of them
+    const dim3 grid((unsigned)std::min<int64_t>((nthreads + 63) / 64, 65536));
     switch (rs) {
-      case 2: hipLaunchKernelGGL(k_ifft_pass<2>, dim3(grid_for(nthreads)), dim3(256), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
-      case 4: hipLaunchKernelGGL(k_ifft_pass<4>, dim3(grid_for(nthreads)), dim3(256), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
-      case 8: hipLaunchKernelGGL(k_ifft_pass<8>, dim3(grid_for(nthreads)), dim3(256), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
-      default: hipLaunchKernelGGL(k_ifft_pass<16>, dim3(grid_for(nthreads)), dim3(256), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
+      case 2: hipLaunchKernelGGL(k_ifft_pass<2>, grid, dim3(64), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
+      case 4: hipLaunchKernelGGL(k_ifft_pass<4>, grid, dim3(64), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
+      case 8: hipLaunchKernelGGL(k_ifft_pass<8>, grid, dim3(64), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
+      default: hipLaunchKernelGGL(k_ifft_pass<16>, grid, dim3(64), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     Ns *= rs;
