@@ -368,7 +368,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the sketch would shard over k with one all-reduce of c; not built).", file=sys.stderr)
         sys.exit(2)
 

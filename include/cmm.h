@@ -56,7 +56,7 @@ extern "C" {
 #define CMM_EINVAL       -1  /* an argument is out of its documented range */
 #define CMM_ENOMEM       -2  /* device memory could not be allocated */
 #define CMM_EHIP         -3  /* a HIP runtime call or kernel launch failed */
-#define CMM_EUNSUPPORTED -4  /* valid request outside what this build handles */
+#define CMM_EUNSUPPORTED -4  /* valid request outside what the library handles */
 #define CMM_ESTATE       -5  /* object in the wrong state (freed, mismatched) */
 
 /* element types of the stored operands */
