@@ -59,7 +59,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5])
+    p.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 4, 5],
+                   help="1 covariance 256 f32, 2 covariance 4096 f32 (default), 3 DCT 8192 bf16, "
+                        "4 covariance 16384 fp8, 5 the batched form (64 bf16 covariance products)")
     p.add_argument("--dtype", default=None, help="override the workload's dtype (f32/bf16/fp8)")
     p.add_argument("--d", type=int, default=None, help="override the number of repetitions")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -345,7 +347,7 @@ def traffic_record(w):
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", "fft_mac_cov4096_f32_traffic.json")
     src = os.path.join(ROOT, "paper_1108_1320_amd", "csrc", "k_fft_mac.hip")
-    if not (w.name == "cfg2" and w.dtype == "f32" and os.path.exists(rec_path)):
+    if not (w.name == "covariance-4096" and w.dtype == "f32" and os.path.exists(rec_path)):
         return None
     rec = json.load(open(rec_path))
     if rec.get("source_sha256_16") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:

@@ -53,7 +53,7 @@ def _product(cmm, ctx, w):
                               scaleB=sB, subtract_diag=w.subtract_diag, n1=w.n1, n3=w.n3, m=w.m)
 
 
-def test_cfg2_covariance_4096_f32(cmm, ctx):
+def test_covariance_4096_f32(cmm, ctx):
     _say("case: covariance n=m=4096 f32 b=2^16 d=5 (whole sketch)")
     w = W.make_workload(2)
     sk = _product(cmm, ctx, w)
@@ -91,7 +91,7 @@ def _sampled_bucket_check(sk, A, B, w, per_rep, zero_diagonal, seed):
     return tabs, worst
 
 
-def test_cfg3_transform_8192_bf16(cmm, ctx):
+def test_transform_8192_bf16(cmm, ctx):
     _say("case: DCT transform n=8192 bf16 b=2^17 d=7 top-16 per column")
     w = W.make_workload(3)
     sk = _product(cmm, ctx, w)
@@ -124,7 +124,7 @@ def test_cfg3_transform_8192_bf16(cmm, ctx):
     _say(f"  spike recall in the per-column top-16: {hits / (w.n3 * w.K):.4f}")
 
 
-def test_cfg4_covariance_16384_fp8(cmm, ctx):
+def test_covariance_16384_fp8(cmm, ctx):
     _say("case: covariance n=m=16384 fp8 b=2^18 d=9 top-256 (sampled)")
     w = W.make_workload(4)
     sk = _product(cmm, ctx, w)

@@ -237,20 +237,24 @@ def _decode_store(store, dtype, scale):
     return store, scale, val.astype(np.float64)
 
 
-# The five workloads of the benchmark plan.  Data seed 1000+cfg, hash seed
-# 2000+cfg.  ``make_workload`` builds them (cfg 5 through ``batched_sizes``).
+# The benchmark workloads, keyed 1 to 4 (key 5, the batched form, is built
+# by ``batched_workloads``).  Data seed 1000 + key, hash seed 2000 + key.
 CONFIGS = {
-    1: dict(kind="cov", n=256, m=256, pairs=16, rho=0.9, b=1 << 10, d=1, K=16, dtype="f32"),
-    2: dict(kind="cov", n=4096, m=4096, pairs=64, rho=(0.5, 0.95), b=1 << 16, d=5, K=64, dtype="f32"),
-    3: dict(kind="transform", n=8192, spikes=16, noise=1e-3, b=1 << 17, d=7, K=16, dtype="bf16"),
-    4: dict(kind="cov", n=16384, m=16384, pairs=256, rho=(0.5, 0.95), b=1 << 18, d=9, K=256, dtype="fp8"),
+    1: dict(name="covariance-256", kind="cov", n=256, m=256, pairs=16, rho=0.9, b=1 << 10, d=1, K=16,
+            dtype="f32"),
+    2: dict(name="covariance-4096", kind="cov", n=4096, m=4096, pairs=64, rho=(0.5, 0.95), b=1 << 16, d=5,
+            K=64, dtype="f32"),
+    3: dict(name="dct-8192", kind="transform", n=8192, spikes=16, noise=1e-3, b=1 << 17, d=7, K=16,
+            dtype="bf16"),
+    4: dict(name="covariance-16384", kind="cov", n=16384, m=16384, pairs=256, rho=(0.5, 0.95), b=1 << 18,
+            d=9, K=256, dtype="fp8"),
 }
 
 
-def make_workload(cfg: int, n: int | None = None, dtype: str | None = None) -> Workload:
-    """Build workload ``cfg``; ``n`` optionally shrinks it (same recipe, m = n,
-    b scaled to keep b/n) for tests that must run quickly."""
-    c = dict(CONFIGS[cfg])
+def make_workload(key: int, n: int | None = None, dtype: str | None = None) -> Workload:
+    """Build benchmark workload ``key``; ``n`` optionally shrinks it (same
+    recipe, m = n, b scaled to keep b/n) for tests that must run quickly."""
+    c = dict(CONFIGS[key])
     if n is not None and n != c["n"]:
         ratio = c["b"] // c["n"]
         c["b"] = max(16, next_pow2(ratio * n))
@@ -258,12 +262,12 @@ def make_workload(cfg: int, n: int | None = None, dtype: str | None = None) -> W
         c["n"] = n
         c["m"] = n
     dt = dtype or c["dtype"]
-    name = f"cfg{cfg}"
+    name = c["name"]
     if c["kind"] == "cov":
         return covariance_workload(name, c["n"], c.get("m", c["n"]), c["pairs"], c["rho"], c["b"], c["d"],
-                                   c["K"], dt, 1000 + cfg, 2000 + cfg)
+                                   c["K"], dt, 1000 + key, 2000 + key)
     return transform_workload(name, c["n"], c["spikes"], c["noise"], c["b"], c["d"], c["K"], dt,
-                              1000 + cfg, 2000 + cfg)
+                              1000 + key, 2000 + key)
 
 
 def batched_sizes(count: int = 64, seed: int = 1005, lo: int = 512, hi: int = 8192):
@@ -287,7 +291,7 @@ def batched_workloads(count: int = 64, seed: int = 1005, lo: int = 512, hi: int 
     ``dtype``), each selecting its top-(planted pairs) over i < j."""
     out = []
     for p, (n, b, pairs, data_seed, hash_seed) in enumerate(batched_sizes(count, seed, lo, hi)):
-        out.append(covariance_workload(f"cfg5.{p}", n, n, pairs, (0.5, 0.95), b, d, pairs, dtype,
+        out.append(covariance_workload(f"batched-64.{p}", n, n, pairs, (0.5, 0.95), b, d, pairs, dtype,
                                        data_seed, hash_seed))
     return out
 
