@@ -144,6 +144,69 @@ __global__ __launch_bounds__(1024) void k_segment_rank(const int32_t* __restrict
   if (tid == 0) segcount[t * W + w] = base;
 }
 
+// The same ranking with one block per (chunk of 1024 segment entries,
+// segment w, repetition t): a block first counts the non-empty buckets of
+// the earlier chunks of its segment (its base rank), so all chunks rank at
+// once.  Used while a segment has at most kRankChunks chunks (the recount
+// grows with the square of their number).
+constexpr int kRankChunks = 32;
+
+__global__ __launch_bounds__(1024) void k_segment_rank_chunks(const int32_t* __restrict__ cnt,
+                                                              int64_t b, int log2c, int T, int G, int W,
+                                                              int Lcap, int Lrow, int32_t* __restrict__ pos,
+                                                              uint32_t* __restrict__ ent,
+                                                              int32_t* __restrict__ cntp,
+                                                              int32_t* __restrict__ segcount,
+                                                              int32_t* __restrict__ overflow) {
+  const int chunk = blockIdx.x, w = blockIdx.y, t = blockIdx.z;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  __shared__ int wave_tot[16];
+  __shared__ int wave_pre[16];
+  const int64_t nseg = b / W;
+  const int32_t* cnt_t = cnt + (int64_t)t * b;
+  auto bucket = [&](int64_t e) { return (e / G) * T + (int64_t)w * G + (e % G); };
+  // base rank: non-empty buckets of the segment before this chunk
+  int before = 0;
+  for (int64_t e = tid; e < (int64_t)chunk * 1024; e += 1024) before += cnt_t[bucket(e)] > 0;
+  for (int off = 32; off > 0; off >>= 1) before += __shfl_xor(before, off, 64);
+  if (lane == 0) wave_tot[wv] = before;
+  __syncthreads();
+  int base = 0;
+  for (int i = 0; i < 16; ++i) base += wave_tot[i];
+  __syncthreads();
+  // rank within the chunk, as k_segment_rank does for one chunk
+  const int64_t e = (int64_t)chunk * 1024 + tid;
+  const bool valid = e < nseg;
+  const int64_t u = bucket(e);
+  const int c = valid ? cnt_t[u] : 0;
+  const bool occ = c > 0;
+  const uint64_t bal = __ballot(occ);
+  const int lrank = __popcll(bal & ((1ull << lane) - 1ull));
+  if (lane == 0) wave_tot[wv] = __popcll(bal);
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int i = 0; i < 16; ++i) { wave_pre[i] = acc; acc += wave_tot[i]; }
+    wave_tot[0] = acc;
+  }
+  __syncthreads();
+  const int rank = base + wave_pre[wv] + lrank;
+  int32_t* pos_t = pos + (int64_t)t * b;
+  uint32_t* ent_t = ent + (int64_t)t * Lrow + (int64_t)w * Lcap;
+  int32_t* cntp_t = cntp + (int64_t)t * Lrow + (int64_t)w * Lcap;
+  if (valid) {
+    if (occ && rank < Lcap) {
+      pos_t[u] = w * Lcap + rank;
+      ent_t[rank] = fold_entry((uint32_t)u, log2c);
+      cntp_t[rank] = c;
+    } else {
+      pos_t[u] = -1;
+      if (occ) atomicExch(overflow, 1);
+    }
+  }
+  if (tid == 0 && (int64_t)(chunk + 1) * 1024 >= nseg) segcount[t * W + w] = base + wave_tot[0];
+}
+
 // One block per repetition: segment padding, per-position member offsets.
 __global__ __launch_bounds__(1024) void k_layout_finish(int W, int G, int Lcap, int Lrow,
                                                         const int32_t* __restrict__ segcount,
@@ -247,8 +310,14 @@ __global__ void k_build_tab(const int32_t* __restrict__ hs, int d, int n, int W,
 
 hipError_t launch_layout(const Geometry& g, SideDesc& sd, int32_t* overflow, hipStream_t s) {
   hipError_t e;
-  hipLaunchKernelGGL(k_segment_rank, dim3(g.W, g.d), dim3(1024), 0, s, sd.cnt, g.b, g.log2c, g.T, g.G,
-                     g.W, sd.Lcap, sd.Lrow, sd.pos, sd.ent, sd.cntp, sd.segcount, overflow);
+  const int64_t nchunks = (g.b / g.W + 1023) / 1024;
+  if (nchunks <= kRankChunks)
+    hipLaunchKernelGGL(k_segment_rank_chunks, dim3((unsigned)nchunks, g.W, g.d), dim3(1024), 0, s, sd.cnt,
+                       g.b, g.log2c, g.T, g.G, g.W, sd.Lcap, sd.Lrow, sd.pos, sd.ent, sd.cntp,
+                       sd.segcount, overflow);
+  else
+    hipLaunchKernelGGL(k_segment_rank, dim3(g.W, g.d), dim3(1024), 0, s, sd.cnt, g.b, g.log2c, g.T, g.G,
+                       g.W, sd.Lcap, sd.Lrow, sd.pos, sd.ent, sd.cntp, sd.segcount, overflow);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_layout_finish, dim3(g.d), dim3(1024), 0, s, g.W, g.G, sd.Lcap, sd.Lrow,
                      sd.segcount, sd.lseg, sd.ent, sd.tab, sd.cntp, sd.moff);

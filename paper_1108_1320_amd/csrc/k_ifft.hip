@@ -15,22 +15,38 @@
 
 namespace cmm {
 
-// Psum[t][f1][f2] = sum over ks of Ppart[t][ks][f1][f2]
+// Psum[t][f1][f2] = sum over ks of Ppart[t][ks][f1][f2], each element's sum
+// in increasing ks.  A thread sums two neighbouring elements (16-byte loads;
+// C is even) with eight k-splits' loads issued ahead of their adds.
 __global__ void k_reduce_splits(const float2* __restrict__ Ppart, int KS, int rows, int C,
                                 int d, double2* __restrict__ Psum) {
   const int64_t per_t = (int64_t)rows * C;
-  const int64_t total = (int64_t)d * per_t;
+  const int64_t pairs = per_t / 2;
+  const int64_t total = (int64_t)d * pairs;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    const int t = (int)(idx / per_t);
-    const int64_t rest = idx - (int64_t)t * per_t;
-    const float2* src = Ppart + (int64_t)t * KS * per_t + rest;
-    double sx = 0.0, sy = 0.0;
-    for (int ks = 0; ks < KS; ++ks) {
-      const float2 v = src[(int64_t)ks * per_t];
-      sx += (double)v.x; sy += (double)v.y;
+    const int t = (int)(idx / pairs);
+    const int64_t rest = 2 * (idx - (int64_t)t * pairs);
+    const float4* src = reinterpret_cast<const float4*>(Ppart + (int64_t)t * KS * per_t + rest);
+    const int64_t stride = per_t / 2;   // one k-split, in float4
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int ks = 0;
+    for (; ks + 8 <= KS; ks += 8) {
+      float4 v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = src[(int64_t)(ks + q) * stride];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        s0 += (double)v[q].x; s1 += (double)v[q].y; s2 += (double)v[q].z; s3 += (double)v[q].w;
+      }
     }
-    Psum[idx] = make_double2(sx, sy);
+    for (; ks < KS; ++ks) {
+      const float4 v = src[(int64_t)ks * stride];
+      s0 += (double)v.x; s1 += (double)v.y; s2 += (double)v.z; s3 += (double)v.w;
+    }
+    double2* dst = Psum + (int64_t)t * per_t + rest;
+    dst[0] = make_double2(s0, s1);
+    dst[1] = make_double2(s2, s3);
   }
 }
 
@@ -98,7 +114,7 @@ static inline unsigned grid_for(int64_t n, int64_t cap = 16384) {
 hipError_t launch_ifft(const Geometry& g, const float2* Ppart, double2* work0, double2* work1,
                        const double2* tw64, double* c64, hipStream_t s) {
   const int C = 1 << g.log2c;
-  const int64_t nsum = (int64_t)g.d * g.rows * C;
+  const int64_t nsum = (int64_t)g.d * g.rows * C / 2;   // element pairs
   // Psum lives in work1 (size d*b >= d*rows*C), the assembled spectrum in work0
   hipLaunchKernelGGL(k_reduce_splits, dim3(grid_for(nsum)), dim3(256), 0, s, Ppart, g.KS,
                      g.rows, C, g.d, work1);
