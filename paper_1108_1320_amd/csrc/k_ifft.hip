@@ -4,10 +4,11 @@
 //
 // The FFT kernel leaves, per k-split, rows f1 in [0, R/2] of the spectrum
 // (frequency f = f1 + R f2).  The reduction sums the k-splits in a fixed
-// order and rebuilds the full length-b spectrum from Hermitian symmetry:
-// for f1 > R/2, P[f1 + R f2] = conj P[(R - f1) + R (C - 1 - f2)].  The
-// inverse DFT then runs as global-memory Stockham passes (radix 16 with one
-// smaller first pass), and c_t[u] = Re(.)/b.
+// order.  The inverse DFT runs as global-memory Stockham passes (radix 16
+// with one smaller first pass): the first reads the full length-b spectrum
+// through Hermitian symmetry, for f1 > R/2
+// P[f1 + R f2] = conj P[(R - f1) + R (C - 1 - f2)], and the last writes
+// c_t[u] = Re(.)/b.
 #include "cmm_internal.h"
 #include "cmm_dft.h"
 
@@ -50,28 +51,34 @@ __global__ void k_reduce_splits(const float2* __restrict__ Ppart, int KS, int ro
   }
 }
 
-__global__ void k_assemble(const double2* __restrict__ Psum, int R, int rows, int C, int64_t b,
-                           int d, double2* __restrict__ P) {
-  const int64_t total = (int64_t)d * b;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int t = (int)(idx / b);
-    const int64_t f = idx - (int64_t)t * b;
-    int f1 = (int)(f & (R - 1));
-    int64_t f2 = f / R;
-    bool cj = false;
-    if (R > 1 && 2 * f1 > R) { f1 = R - f1; f2 = C - 1 - f2; cj = true; }
-    double2 v = Psum[((int64_t)t * rows + f1) * C + f2];
-    if (cj) v.y = -v.y;
-    P[idx] = v;
-  }
+// Spectrum value P_t[f] from the k-split sums: rows f1 <= R/2 are stored,
+// the others are the conjugates of their Hermitian mirrors.
+__device__ __forceinline__ double2 assembled(const double2* __restrict__ Psum, int t, int64_t f,
+                                             int R, int rows, int C) {
+  int f1 = (int)(f & (R - 1));
+  int64_t f2 = f / R;
+  bool cj = false;
+  if (R > 1 && 2 * f1 > R) { f1 = R - f1; f2 = C - 1 - f2; cj = true; }
+  double2 v = Psum[((int64_t)t * rows + f1) * C + f2];
+  if (cj) v.y = -v.y;
+  return v;
 }
+
+struct IfftEnds {
+  const double2* Psum;   // FIRST: read the spectrum from the k-split sums
+  int R, rows, C;
+  double* c;             // LAST: write Re(.) / b as the sketch
+  double inv_b;
+};
 
 // One inverse Stockham pass of radix RS over every repetition:
 // out[(jb/Ns) Ns RS + jb mod Ns + r Ns] = IDFT_RS( in[jb + r b/RS] conj(w) ).
-template <int RS>
+// The first pass reads the assembled spectrum, the last writes the real
+// sketch c_t[u] = Re(x_t[u]) / b.
+template <int RS, bool FIRST, bool LAST>
 __global__ void k_ifft_pass(const double2* __restrict__ in, double2* __restrict__ out,
-                            const double2* __restrict__ tw, int64_t b, int d, int64_t Ns) {
+                            const double2* __restrict__ tw, int64_t b, int d, int64_t Ns,
+                            IfftEnds ends) {
   const int64_t nb = b / RS;
   const int64_t total = (int64_t)d * nb;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
@@ -79,29 +86,30 @@ __global__ void k_ifft_pass(const double2* __restrict__ in, double2* __restrict_
     const int t = (int)(idx / nb);
     const int64_t jb = idx - (int64_t)t * nb;
     const double2* src = in + (int64_t)t * b;
-    double2* dst = out + (int64_t)t * b;
     const int64_t jm = jb % Ns;
     const int64_t step = b / (Ns * RS);
     double2 x[RS];
 #pragma unroll
     for (int r = 0; r < RS; ++r) {
       // inverse = conj(DFT(conj(x) * w)), with twiddle w^(jm r)
-      double2 v = cconj(src[jb + (int64_t)r * nb]);
+      double2 v = FIRST ? assembled(ends.Psum, t, jb + (int64_t)r * nb, ends.R, ends.rows, ends.C)
+                        : src[jb + (int64_t)r * nb];
+      v = cconj(v);
       if (r > 0 && jm > 0) v = cmul(v, tw[(jm * r * step) & (b - 1)]);
       x[r] = v;
     }
     dft<RS>(x);
     const int64_t base = (jb / Ns) * Ns * RS + jm;
+    if constexpr (LAST) {
+      double* c = ends.c + (int64_t)t * b;
 #pragma unroll
-    for (int r = 0; r < RS; ++r) dst[base + (int64_t)r * Ns] = cconj(x[r]);
+      for (int r = 0; r < RS; ++r) c[base + (int64_t)r * Ns] = x[r].x * ends.inv_b;
+    } else {
+      double2* dst = out + (int64_t)t * b;
+#pragma unroll
+      for (int r = 0; r < RS; ++r) dst[base + (int64_t)r * Ns] = cconj(x[r]);
+    }
   }
-}
-
-__global__ void k_real_part(const double2* __restrict__ z, double inv_b, int64_t count,
-                            double* __restrict__ c) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    c[i] = z[i].x * inv_b;
 }
 
 static inline unsigned grid_for(int64_t n, int64_t cap = 16384) {
@@ -115,37 +123,45 @@ hipError_t launch_ifft(const Geometry& g, const float2* Ppart, double2* work0, d
                        const double2* tw64, double* c64, hipStream_t s) {
   const int C = 1 << g.log2c;
   const int64_t nsum = (int64_t)g.d * g.rows * C / 2;   // element pairs
-  // Psum lives in work1 (size d*b >= d*rows*C), the assembled spectrum in work0
+  // Psum lives in work1 (size d*b >= d*rows*C)
   hipLaunchKernelGGL(k_reduce_splits, dim3(grid_for(nsum)), dim3(256), 0, s, Ppart, g.KS,
                      g.rows, C, g.d, work1);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_assemble, dim3(grid_for((int64_t)g.d * g.b)), dim3(256), 0, s, work1,
-                     g.R, g.rows, C, g.b, g.d, work0);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  double2* src = work0;
-  double2* dst = work1;
+  // the first pass reads Psum; the passes then alternate work0 / work1
+  IfftEnds ends{work1, g.R, g.rows, C, c64, 1.0 / (double)g.b};
+  double2* src = work1;   // unused by the first pass
+  double2* dst = work0;
   int64_t Ns = 1;
   const int rem = g.log2b % 4;
-  int passes = g.log2b / 4 + (rem ? 1 : 0);
+  const int passes = g.log2b / 4 + (rem ? 1 : 0);
   for (int p = 0; p < passes; ++p) {
     const int rs = (p == 0 && rem) ? (1 << rem) : 16;
     const int64_t nthreads = (int64_t)g.d * (g.b / rs);
     // one wave per block: d * b / 16 butterflies are only a few hundred
     // waves, which then spread over every CU instead of a quarter of them
     const dim3 grid((unsigned)std::min<int64_t>((nthreads + 63) / 64, 65536));
+    const bool first = p == 0, last = p == passes - 1;
+#define CMM_IF(RS_, F_, L_) hipLaunchKernelGGL((k_ifft_pass<RS_, F_, L_>), grid, dim3(64), 0, s, src, dst, tw64, g.b, g.d, Ns, ends)
+#define CMM_IF_RS(RS_) \
+    if (first && last) CMM_IF(RS_, true, true); \
+    else if (first) CMM_IF(RS_, true, false); \
+    else if (last) CMM_IF(RS_, false, true); \
+    else CMM_IF(RS_, false, false);
     switch (rs) {
-      case 2: hipLaunchKernelGGL(k_ifft_pass<2>, grid, dim3(64), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
-      case 4: hipLaunchKernelGGL(k_ifft_pass<4>, grid, dim3(64), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
-      case 8: hipLaunchKernelGGL(k_ifft_pass<8>, grid, dim3(64), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
-      default: hipLaunchKernelGGL(k_ifft_pass<16>, grid, dim3(64), 0, s, src, dst, tw64, g.b, g.d, Ns); break;
+      case 2: CMM_IF_RS(2) break;
+      case 4: CMM_IF_RS(4) break;
+      case 8: CMM_IF_RS(8) break;
+      default: CMM_IF_RS(16) break;
     }
+#undef CMM_IF_RS
+#undef CMM_IF
     if ((e = hipGetLastError()) != hipSuccess) return e;
     Ns *= rs;
-    double2* tmpb = src; src = dst; dst = tmpb;
+    // the first pass read Psum (work1) and wrote work0; then ping-pong
+    if (first) { src = work0; dst = work1; }
+    else { double2* tmpb = src; src = dst; dst = tmpb; }
   }
-  hipLaunchKernelGGL(k_real_part, dim3(grid_for((int64_t)g.d * g.b)), dim3(256), 0, s, src,
-                     1.0 / (double)g.b, (int64_t)g.d * g.b, c64);
   return hipGetLastError();
 }
 
