@@ -682,8 +682,13 @@ int check_dims(cmm_ctx* c, int64_t n1, int64_t m, int64_t n3, int64_t b, int32_t
 
 // Mean time of one product under tuning `tu` on the synthetic operands of
 // `sk` (5 back-to-back runs after a warm-up run on the context stream).
+// With `cs_only` the timed runs are the two count-sketch launches alone, 10
+// pairs after the warm-up product has built the layout they read: the
+// number of count-sketch blocks changes nothing else, and its effect is a
+// few per cent of a product, below the noise of whole-product timing.
 int time_candidate(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Tuning& tu,
-                   const uint64_t* pdev, hipEvent_t ev0, hipEvent_t ev1, double* ms) {
+                   const uint64_t* pdev, hipEvent_t ev0, hipEvent_t ev1, double* ms,
+                   bool cs_only = false) {
   hipStream_t s = c->stream;
   const cmm::Geometry g = make_geometry(sk->b, sk->d, sk->m, tu);
   for (int attempt = 0; attempt < 2; ++attempt) {
@@ -698,13 +703,21 @@ int time_candidate(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Tu
     if (rc == CMM_OK && hipStreamSynchronize(s) != hipSuccess)
       rc = fail(c, CMM_EHIP, "stream synchronisation failed");
     if (rc == CMM_OK && c->pinned_u32[0] != 0 && attempt == 0) { ws_release(c, owned); continue; }
+    const int reps = cs_only ? 10 : 5;
+    cmm::SideDesc side[2];
+    if (cs_only) bind_sides(g, sk, op, spec, ptr, side);
     if (rc == CMM_OK && hipEventRecord(ev0, s) != hipSuccess) rc = fail(c, CMM_EHIP, "event record failed");
-    for (int r = 0; r < 5 && rc == CMM_OK; ++r) rc = enqueue_product(c, sk, op, g, spec, ptr, pdev, s);
+    for (int r = 0; r < reps && rc == CMM_OK; ++r) {
+      if (!cs_only) { rc = enqueue_product(c, sk, op, g, spec, ptr, pdev, s); continue; }
+      for (int q = 0; q < 2 && rc == CMM_OK; ++q)
+        if (cmm::launch_countsketch(op.dtype, g, side[q], s) != hipSuccess)
+          rc = fail(c, CMM_EHIP, "countsketch launch failed");
+    }
     if (rc == CMM_OK && hipEventRecord(ev1, s) != hipSuccess) rc = fail(c, CMM_EHIP, "event record failed");
     if (rc == CMM_OK && hipEventSynchronize(ev1) != hipSuccess) rc = fail(c, CMM_EHIP, "event wait failed");
     float t = 0.f;
     if (rc == CMM_OK && hipEventElapsedTime(&t, ev0, ev1) != hipSuccess) rc = fail(c, CMM_EHIP, "event time failed");
-    if (rc == CMM_OK) *ms = t / 5.0;
+    if (rc == CMM_OK) *ms = t / reps;
     (void)hipStreamSynchronize(s);
     ws_release(c, owned);
     return rc;
@@ -713,10 +726,12 @@ int time_candidate(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Tu
 }
 
 // Coordinate search over the geometry of one size class: the FFT row
-// length first, then the number of k per spectral block, then the number
-// of count-sketch blocks, starting from the built-in default; candidates
-// that give the same launch shapes as one already timed are skipped, and a
-// candidate replaces the incumbent only when at least 3 % faster.
+// length first, then the number of k per spectral block (both timed as
+// whole products), then the number of count-sketch blocks (timed on the
+// count-sketch launches alone), starting from the built-in default;
+// candidates that give the same launch shapes as one already timed are
+// skipped, and a candidate replaces the incumbent only when at least 3 %
+// faster.  The recorded time is that of a whole product with the result.
 int autotune_class(cmm_ctx* c, int64_t n1, int64_t m, int64_t n3, int64_t b, int d, int dtype,
                    TuneEntry* best) {
   hipStream_t s = c->stream;
@@ -754,20 +769,26 @@ int autotune_class(cmm_ctx* c, int64_t n1, int64_t m, int64_t n3, int64_t b, int
     const std::vector<int> vals = axis == 0 ? std::vector<int>{10, 11, 12, 13}
                                 : axis == 1 ? std::vector<int>{32, 64, 128}
                                             : std::vector<int>{512, 1024, 2048, 4096};
+    const bool cs_only = axis == 2;
     const cmm::Tuning base = cur;
+    double base_ms = cur_ms;
+    if (cs_only) rc = time_candidate(c, sk, op, base, pdev, ev0, ev1, &base_ms, true);
     for (int v : vals) {
+      if (rc != CMM_OK) break;
       cmm::Tuning t = base;
       (axis == 0 ? t.log2c : axis == 1 ? t.kmax : t.cs_blocks) = v;
       const auto sh = shape(t);
       if (std::find(seen.begin(), seen.end(), sh) != seen.end()) continue;
       seen.push_back(sh);
       double ms = 0.0;
-      rc = time_candidate(c, sk, op, t, pdev, ev0, ev1, &ms);
+      rc = time_candidate(c, sk, op, t, pdev, ev0, ev1, &ms, cs_only);
       if (rc != CMM_OK) break;
       // a candidate must be clearly faster than the incumbent (timing noise
       // between runs is a few per cent)
-      if (ms < 0.97 * cur_ms) { cur = t; cur_ms = ms; }
+      if (ms < 0.97 * base_ms) { cur = t; base_ms = ms; if (!cs_only) cur_ms = ms; }
     }
+    if (rc == CMM_OK && cs_only && cur.cs_blocks != base.cs_blocks)
+      rc = time_candidate(c, sk, op, cur, pdev, ev0, ev1, &cur_ms);
   }
   c->prof = prof;
   (void)hipStreamSynchronize(s);
