@@ -446,6 +446,7 @@ def main():
         "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in kern.items()},
         "roofline": {
             "kernel": "fft_mac",
+            "kernels": ["k_fft_mac", "k_fft_mac_pair"],
             "bound": "alu",
             "achieved": round(achieved_tflops, 3),
             "peak": FP32_VECTOR_PEAK_TFLOPS,

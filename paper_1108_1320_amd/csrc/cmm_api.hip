@@ -58,6 +58,7 @@ struct cmm_ctx {
   std::string arch;
   int64_t ws_limit = 0;     // workspace limit of one product in bytes (0: ws_default)
   int64_t ws_default = 0;   // half the device memory
+  cmm::Overlap ov;          // second stream of the spectral step
 };
 
 struct cmm_sketch {
@@ -76,6 +77,13 @@ struct cmm_sketch {
 };
 
 namespace {
+
+void destroy_overlap(cmm::Overlap& ov) {
+  if (ov.aux) { hipStreamSynchronize(ov.aux); hipStreamDestroy(ov.aux); }
+  if (ov.fork) hipEventDestroy(ov.fork);
+  if (ov.join) hipEventDestroy(ov.join);
+  ov = cmm::Overlap();
+}
 
 int fail(cmm_ctx* c, int code, const std::string& msg) {
   if (c) c->last_error = msg;
@@ -236,7 +244,8 @@ cmm::Geometry make_geometry(int64_t b, int d, int64_t m, const cmm::Tuning& tu) 
   g.W = g.T / g.G;
   g.R = (int)(b / C);
   g.rows = g.R > 1 ? g.R / 2 + 1 : 1;
-  const int64_t base = (int64_t)d * g.rows;
+  g.rblocks = g.R > 1 ? g.R / 2 : 1;
+  const int64_t base = (int64_t)d * g.rblocks;
   const int kmax = std::max(1, std::min(tu.kmax, cmm::kMaxKPerBlock));
   int64_t ks = std::max<int64_t>(1, (2048 + base - 1) / base);
   ks = std::max<int64_t>(ks, (m + kmax - 1) / kmax);
@@ -455,7 +464,8 @@ int enqueue_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::G
   }
   {
     Scope sc_(c, "fft_mac");
-    CMM_HIP(c, cmm::launch_fft_mac(g, side[0], side[1], tw32, (float2*)ptr.p[W_PPART], s));
+    CMM_HIP(c, cmm::launch_fft_mac(g, side[0], side[1], tw32, (float2*)ptr.p[W_PPART], s,
+                                   s == c->stream ? &c->ov : nullptr));
   }
   {
     Scope sc_(c, "ifft");
@@ -889,7 +899,7 @@ struct BatchItem {
 // count-sketch work over the hashed entries.
 double product_cost(const cmm::Geometry& g, int64_t n1, int64_t n3) {
   const double C = (double)(1 << g.log2c);
-  return (double)g.d * g.m * (2.0 * g.rows * C * g.log2c + 8.0 * (n1 + n3));
+  return (double)g.d * g.m * (2.0 * g.rblocks * C * g.log2c + 8.0 * (n1 + n3));
 }
 
 int build_batch(cmm_ctx* c, const cmm_problem* pr, int count, uint32_t flags, cmm_batch* bt) {
@@ -1065,7 +1075,11 @@ int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out) {
   c->ws_default = hipMemGetInfo(&mem_free, &mem_total) == hipSuccess && mem_total > 0
                       ? (int64_t)(mem_total / 2) : (int64_t)64 << 30;
   if (cmm::prepare_countsketch() != hipSuccess || cmm::prepare_fft_mac() != hipSuccess ||
-      cmm::prepare_sparse() != hipSuccess || cmm::prepare_decode() != hipSuccess) {
+      cmm::prepare_sparse() != hipSuccess || cmm::prepare_decode() != hipSuccess ||
+      hipStreamCreateWithFlags(&c->ov.aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ov.fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ov.join, hipEventDisableTiming) != hipSuccess) {
+    destroy_overlap(c->ov);
     hipHostFree(c->pinned_u32);
     hipHostFree(c->pinned);
     delete c;
@@ -1094,6 +1108,7 @@ int cmm_ctx_destroy(cmm_ctx* ctx) {
   if (!valid_ctx(ctx)) return CMM_EINVAL;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
+  destroy_overlap(ctx->ov);
   for (auto& p : ctx->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
   for (auto& kv : ctx->sizes) hipFree(kv.first);
   for (auto& kv : ctx->twiddles) { hipFree(kv.second.first); hipFree(kv.second.second); }
@@ -1715,7 +1730,8 @@ int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B
         CMM_HIP(ctx, cmm::launch_code_mask((int)nn[q], Ls[q], r, scl[q], mask, s));
         side[q].scale = mask;
         CMM_HIP(ctx, cmm::launch_countsketch(dtype, g, side[q], s));
-        CMM_HIP(ctx, cmm::launch_fft_mac(g, side[0], side[1], tw32, (float2*)ptr.p[W_PPART], s));
+        CMM_HIP(ctx, cmm::launch_fft_mac(g, side[0], side[1], tw32, (float2*)ptr.p[W_PPART], s,
+                                         s == ctx->stream ? &ctx->ov : nullptr));
         CMM_HIP(ctx, cmm::launch_ifft(g, (float2*)ptr.p[W_PPART], (double2*)ptr.p[W_WORK0],
                                       (double2*)ptr.p[W_WORK1], tw64, ctmp, s));
         if (diagm) {

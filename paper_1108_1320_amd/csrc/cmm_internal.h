@@ -154,6 +154,8 @@ struct Geometry {
   int W;                // segments = T / G
   int R;                // rows of the four-step split = b / C
   int rows;             // computed rows (R/2 + 1, or 1 when R == 1)
+  int rblocks;          // FFT blocks per (repetition, k-split): R/2 (rows 0
+                        // and R/2 share one), or 1 when R == 1
   int KS;               // k-splits of the FFT kernel
   int cs_blocks;        // countsketch blocks
 };
@@ -169,8 +171,16 @@ hipError_t prepare_countsketch();
 hipError_t prepare_fft_mac();
 hipError_t prepare_decode();
 hipError_t launch_countsketch(int dtype, const Geometry& g, SideDesc& sd, hipStream_t s);
+// A second stream and two events with which the row-pair kernel of the
+// spectral step runs beside the row kernel (a fork from and a join back to
+// the launching stream).
+struct Overlap {
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
 hipError_t launch_fft_mac(const Geometry& g, const SideDesc& a, const SideDesc& bside,
-                          const float2* tw32, float2* Ppart, hipStream_t s);
+                          const float2* tw32, float2* Ppart, hipStream_t s,
+                          const Overlap* ov = nullptr);
 hipError_t launch_ifft(const Geometry& g, const float2* Ppart, double2* work0, double2* work1,
                        const double2* tw64, double* c64, hipStream_t s);
 hipError_t launch_diag(int dtype, const SideDesc& a, const SideDesc& bside, int m, int n,

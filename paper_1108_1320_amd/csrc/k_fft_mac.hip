@@ -55,7 +55,7 @@ struct FftArgs {
   const float2* tw;        // omega_b^x for x < b
   float2* Ppart;
   int64_t b;
-  int R, rows, d, m, KS, nwg, remap;
+  int R, rows, nrow, roff, d, m, KS, nwg, remap;
 };
 
 constexpr int ipow16(int e) { return e <= 0 ? 1 : 16 * ipow16(e - 1); }
@@ -189,18 +189,46 @@ template <typename V> __device__ __forceinline__ const V& at_byte(const V* base,
   return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + off);
 }
 
+// omega_32^q = exp(-2 pi i q / 32) for q < 16 (cos, sin of q pi / 16)
+constexpr float kW32[16][2] = {
+    {1.0f, 0.0f}, {0.98078528040323043f, -0.19509032201612825f},
+    {0.92387953251128674f, -0.38268343236508978f}, {0.83146961230254524f, -0.55557023301960218f},
+    {0.70710678118654757f, -0.70710678118654746f}, {0.55557023301960229f, -0.83146961230254524f},
+    {0.38268343236508984f, -0.92387953251128674f}, {0.19509032201612833f, -0.98078528040323043f},
+    {0.0f, -1.0f}, {-0.19509032201612819f, -0.98078528040323043f},
+    {-0.38268343236508973f, -0.92387953251128674f}, {-0.55557023301960196f, -0.83146961230254546f},
+    {-0.70710678118654746f, -0.70710678118654757f}, {-0.83146961230254535f, -0.55557023301960218f},
+    {-0.92387953251128674f, -0.38268343236508989f}, {-0.98078528040323043f, -0.19509032201612861f},
+};
+
+// Fold modes: the single row of R == 1 (unit weights), a weighted row f1
+// in [1, R/2), and the row pair {0, R/2} (see below).
+enum { kFoldRow0 = 0, kFoldRow = 1, kFoldPair = 2 };
+
+// Row pair {0, R/2}.  Row 0 holds the spectrum at multiples of R and row R/2
+// at odd multiples of R/2; both are the length-2C DFT of the real sequence
+// p[r'] = sum of x[u] over u = r' (mod 2C), at even and odd frequencies.
+// That DFT comes from one C-point complex FFT of z[s] = p[2s] + i p[2s+1]:
+// with Z = FFT(z) and Zm[f] = Z[(C - f) mod C],
+//   P[f]     = (Z[f] + conj Zm[f]) / 2 + omega_2C^f (Z[f] - conj Zm[f]) / (2i),
+//   P[C]     = Re Z[0] - Im Z[0],
+// and P[2C - f] = conj P[f].  Bucket u folds with weight 1 into slot
+// s = (u mod 2C) div 2, real part for even u mod 2C and imaginary part for
+// odd.  Slot s belongs to thread s mod T, in general not in the wave of
+// the entry, so this fold is bracketed by block barriers.
+
 // The batch is folded in groups of 4 entries (the last group may be
 // shorter): a group that lies wholly past the segment is skipped by a
 // wave-uniform test; inside a group there is no branch, so the weight reads
 // issue together.  Padding entries carry value 0 and an own slot of the
-// wave.  Row 0 has unit weights (ROW0).
-template <int kU, bool ROW0>
+// wave.  CH = C / 2 (used by the pair mode).
+template <int kU, int MODE, int CH>
 __device__ __forceinline__ void fold_group(const Batch<kU>& bt, int g0, unsigned long long* Z,
                                            const float2* wf, float scale) {
   constexpr int kG = 4;
   const int gn = kU - g0 < kG ? kU - g0 : kG;
   float2 w[kG];
-  if constexpr (!ROW0) {
+  if constexpr (MODE == kFoldRow) {
 #pragma unroll
     for (int i = 0; i < kG; ++i)
       if (i < gn) w[i] = at_byte(wf, bt.u[g0 + i] >> 16);
@@ -208,22 +236,33 @@ __device__ __forceinline__ void fold_group(const Batch<kU>& bt, int g0, unsigned
 #pragma unroll
   for (int i = 0; i < kG; ++i) {
     if (i >= gn) break;
-    const uint32_t off = bt.u[g0 + i] & 0xFFFFu;
+    const uint32_t e = bt.u[g0 + i];
+    const uint32_t off = e & 0xFFFFu;
     // |value * scale| < 2^30: float32 keeps 24 bits, so values near the top
     // have no fraction and truncation only touches the smallest ones
     const float sv = bt.v[g0 + i] * scale;
-    if constexpr (ROW0) atomicAdd(&at_byte(Z, off), (unsigned long long)(long long)(int)sv);
-    else atomicAdd(&at_byte(Z, off), pack2((int)(sv * w[i].x), (int)(sv * w[i].y)));
+    if constexpr (MODE == kFoldRow0) {
+      atomicAdd(&at_byte(Z, off), (unsigned long long)(long long)(int)sv);
+    } else if constexpr (MODE == kFoldRow) {
+      atomicAdd(&at_byte(Z, off), pack2((int)(sv * w[i].x), (int)(sv * w[i].y)));
+    } else {
+      // u mod C from the swizzled slot, the parity of u div C from bit 4 of
+      // the weight index; u mod 2C = (u mod C) + C * parity
+      const int rc = fft_swizzle((int)(off >> 3));
+      const int sl = (rc >> 1) + CH * (int)((e >> 23) & 1u);
+      const unsigned long long add = (unsigned long long)(long long)(int)sv;
+      atomicAdd(&Z[fft_swizzle(sl)], (rc & 1) ? add << 32 : add);
+    }
   }
 }
 
-template <int G, int kU, bool ROW0>
+template <int G, int kU, int MODE, int CH>
 __device__ __forceinline__ void fold(const Batch<kU>& bt, unsigned long long* Z,
                                      const float2* wf, float scale, int ls, int first) {
 #pragma unroll
   for (int g0 = 0; g0 < kU; g0 += 4) {
     if ((first + g0) * G >= ls) break;
-    fold_group<kU, ROW0>(bt, g0, Z, wf, scale);
+    fold_group<kU, MODE, CH>(bt, g0, Z, wf, scale);
   }
 }
 
@@ -249,7 +288,7 @@ __device__ __forceinline__ void fetch_group(Batch<kU>& bt, int g0, const float* 
 // group's registers are refilled with the same group of the next batch
 // right after the group is folded, so the next batch's loads are in flight
 // behind the rest of the folding, with no second buffer.
-template <int G, int kU, bool ROW0>
+template <int G, int kU, int MODE, int CH>
 __device__ __forceinline__ void fold_all(Batch<kU>& a, unsigned long long* Z, const float2* wf,
                                          float scale, const float* sa, const uint32_t* en, int ls,
                                          int lane, uint32_t own_off) {
@@ -260,16 +299,174 @@ __device__ __forceinline__ void fold_all(Batch<kU>& a, unsigned long long* Z, co
       const bool whole = (next + kU) * G <= ls;
 #pragma unroll
       for (int g0 = 0; g0 < kU; g0 += 4) {
-        fold_group<kU, ROW0>(a, g0, Z, wf, scale);
+        fold_group<kU, MODE, CH>(a, g0, Z, wf, scale);
         fetch_group<G, kU>(a, g0, sa, en, ls, lane, next, own_off, whole);
       }
     } else {
-      fold<G, kU, ROW0>(a, Z, wf, scale, ls, first);
+      fold<G, kU, MODE, CH>(a, Z, wf, scale, ls, first);
       break;
     }
   }
 }
 
+// One block per (repetition t, k-split ks): the row pair {0, R/2} (R > 1;
+// see the fold modes above).  A kernel of its own, launched beside the row
+// kernel, so that each keeps its own register allocation.
+template <int L>
+__global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
+  typedef FftShape<L> F;
+  const int bid = blockIdx.x;
+  const int logical = a.remap ? (bid & 7) * (a.nwg >> 3) + (bid >> 3) : bid;
+  const int ks = logical % a.KS;
+  const int t = logical / a.KS;
+  constexpr int C = F::C, T = F::T, G = F::G, kU = F::U;
+  extern __shared__ float2 lds[];
+  float2* P0 = lds;
+  float2* P1 = lds + C;
+  float2* tm = lds + 2 * C;
+  const int j = threadIdx.x;
+  const int lane = j % G, wv = j / G;
+  const int R = a.R;
+  const uint64_t bm = (uint64_t)(a.b - 1);
+  const int kb = (int)((int64_t)a.m * ks / a.KS);
+  const int ke = (int)((int64_t)a.m * (ks + 1) / a.KS);
+  const float2 sj = a.tw[((uint64_t)j * (uint64_t)(R >> 1)) & bm];   // omega_2C^j
+  const int jbase = sw(j);
+  // last-stage twiddles omega_C^((j mod Ns) r), Ns = span(S-1)
+  float2 tl[15];
+  if constexpr (F::S >= 2) {
+    constexpr int Ns = F::span(F::S - 1);
+#pragma unroll
+    for (int r = 1; r < 16; ++r)
+      tl[r - 1] = a.tw[(int64_t)((j % Ns) * r) * (C / (16 * Ns)) * R];
+  }
+#pragma unroll
+  for (int s = 1; s < F::S - 1; ++s) {
+    const int Ns = F::span(s);
+    for (int e = j; e < 15 * Ns; e += T) {
+      const int r = e / Ns + 1, jm = e % Ns;
+      tm[F::tmoff(s) + e] = a.tw[(int64_t)(jm * r) * (C / (16 * Ns)) * R];
+    }
+  }
+  unsigned long long* Z = reinterpret_cast<unsigned long long*>(P0);
+  // LDS position of the mirror frequency of j + 15 T when T is a multiple
+  // of 256 (the swizzle then only touches the part below T)
+  const int mirror_base = sw((T - j) & (T - 1)) + (j == 0 ? T : 0);
+  // the first fold adds into other waves' slots: clear before the barrier
+#pragma unroll
+  for (int q = 0; q < 16; ++q) Z[own<T>(jbase, j, q)] = 0ull;
+  __syncthreads();
+
+  float2 acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = make_float2(0.f, 0.f);
+  const float* sa0 = a.SA0 + (int64_t)t * a.m * a.Lrow0 + wv * a.Lcap0;
+  const float* sa1 = a.SA1 + (int64_t)t * a.m * a.Lrow1 + wv * a.Lcap1;
+  const uint32_t* en0 = a.ent0 + (int64_t)t * a.Lrow0 + wv * a.Lcap0;
+  const uint32_t* en1 = a.ent1 + (int64_t)t * a.Lrow1 + wv * a.Lcap1;
+  const int ls0 = a.lseg0[t], ls1 = a.lseg1[t];
+  const float* cm0 = a.cmax0 + (int64_t)t * a.m;
+  const float* cm1 = a.cmax1 + (int64_t)t * a.m;
+  const uint32_t own_off = (uint32_t)jbase * 8u;
+  Batch<kU> bt;
+  if (kb < ke) fetch<G, kU>(bt, sa0 + (int64_t)kb * a.Lrow0, en0, ls0, lane, 0, own_off);
+  const float2* wf = nullptr;   // unused by the pair fold
+  float accn = 0.0f;   // 4 P_A[C] P_B[C] summed (thread 0's is used)
+  for (int k = kb; k < ke; ++k) {
+    float2 X[16];
+    float xn = 0.0f;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const float* sa = side == 0 ? sa0 + (int64_t)k * a.Lrow0 : sa1 + (int64_t)k * a.Lrow1;
+      const uint32_t* en = side == 0 ? en0 : en1;
+      const int ls = side == 0 ? ls0 : ls1;
+      // a slot of the pair gathers at most R/2 buckets: the bound of the
+      // rows holds
+      int ex;
+      const float bound = (float)R * (side == 0 ? cm0[k] : cm1[k]);
+      (void)frexpf(bound, &ex);
+      const float scale = bound > 0.0f ? ldexpf(1.0f, 30 - ex) : 0.0f;
+      const float inv = bound > 0.0f ? ldexpf(1.0f, ex - 30) : 0.0f;
+      fold_all<G, kU, kFoldPair, C / 2>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
+      else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0, own_off);
+      __syncthreads();   // every wave's adds are in
+      float2 v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int2 zi = unpack2(Z[own<T>(jbase, j, q)]);
+        v[q] = make_float2((float)zi.x * inv, (float)zi.y * inv);
+      }
+      Stage<L, 0>::run(v, P0, P1, tl, tm, j);
+      // No thread touches this thread's own positions after the last
+      // stage's barrier: clear the Z slots for the next fold and pass the
+      // spectrum through P1 to the threads holding the mirror frequencies.
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        Z[own<T>(jbase, j, q)] = 0ull;
+        P1[own<T>(jbase, j, q)] = v[q];
+      }
+      __syncthreads();
+      const float nyq = 2.0f * (v[0].x - v[0].y);   // 2 P[C] at thread 0
+      // the 16 twiddles below are loop-invariant; kept opaque so that they
+      // are formed here rather than held in registers across the loop
+      float2 sjk = sj;
+      int mb = mirror_base;
+      asm volatile("" : "+v"(sjk.x), "+v"(sjk.y), "+v"(mb));
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        float2 zm;
+        if constexpr (T % 256 == 0) {
+          // mirror of j + T q: (T - j) + T (15 - q) for j > 0 and
+          // T (16 - q) mod C for j = 0, i.e. mb + T (15 - q), which wraps
+          // to 0 only for j = q = 0
+          zm = q == 0 ? P1[(mb + T * 15) & (C - 1)] : P1[mb + T * (15 - q)];
+        } else {
+          zm = P1[sw((C - (j + T * q)) & (C - 1))];
+        }
+        const float2 ev = make_float2(v[q].x + zm.x, v[q].y - zm.y);   // Z + conj Zm
+        const float2 od = make_float2(v[q].y + zm.y, zm.x - v[q].x);   // -i (Z - conj Zm)
+        // omega_2C^f = omega_2C^j omega_32^q
+        const float2 w = cmul(sjk, make_float2(kW32[q][0], kW32[q][1]));
+        const float2 p2 = cadd(ev, cmul(w, od));                         // 2 P[f]
+        if (side == 0) {
+          X[q] = p2;
+        } else {
+          acc[q].x = fmaf(X[q].x, p2.x, fmaf(-X[q].y, p2.y, acc[q].x));
+          acc[q].y = fmaf(X[q].x, p2.y, fmaf(X[q].y, p2.x, acc[q].y));
+        }
+      }
+      if (side == 0) xn = nyq;
+      else accn = fmaf(xn, nyq, accn);
+    }
+  }
+  // acc holds 4 sum P_A P_B at 2C-frequencies f = j + T q < C, accn at C.
+  // Row 0 position g is frequency 2g and row R/2 position g is 2g + 1;
+  // those at or above C are conjugates of 2C minus them.
+  __syncthreads();   // the last mirror reads are done
+#pragma unroll
+  for (int q = 0; q < 16; ++q) P1[own<T>(jbase, j, q)] = acc[q];
+  if (j == 0) P0[0] = make_float2(accn, 0.0f);
+  __syncthreads();
+  float2* out0 = a.Ppart + ((int64_t)t * a.KS + ks) * a.rows * C;
+  float2* outh = out0 + (int64_t)(R >> 1) * C;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int g = j + T * q;
+    float2 r0, rh;
+    if (2 * g < C) r0 = P1[sw(2 * g)];
+    else if (2 * g == C) r0 = P0[0];
+    else r0 = cconj(P1[sw(2 * (C - g))]);
+    if (2 * g + 1 < C) rh = P1[sw(2 * g + 1)];
+    else rh = cconj(P1[sw(2 * (C - 1 - g) + 1)]);
+    out0[g] = make_float2(0.25f * r0.x, 0.25f * r0.y);
+    outh[g] = make_float2(0.25f * rh.x, 0.25f * rh.y);
+  }
+}
+
+// nrow blocks per (repetition, k-split): rows f1 = roff .. roff + nrow - 1,
+// i.e. 1 .. R/2 - 1 when R > 1 (the pair kernel computes rows 0 and R/2)
+// and row 0 alone when R == 1.
 template <int L>
 __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   typedef FftShape<L> F;
@@ -283,8 +480,8 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
 
   const int bid = blockIdx.x;
   const int logical = a.remap ? (bid & 7) * (a.nwg >> 3) + (bid >> 3) : bid;
-  const int f1 = logical % a.rows;
-  const int tmp = logical / a.rows;
+  const int f1 = logical % a.nrow + a.roff;
+  const int tmp = logical / a.nrow;
   const int ks = tmp % a.KS;
   const int t = tmp / a.KS;
   const int j = threadIdx.x;
@@ -333,6 +530,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   Batch<kU> bt;
   if (kb < ke) fetch<G, kU>(bt, sa0 + (int64_t)kb * a.Lrow0, en0, ls0, lane, 0, own_off);
 
+
   for (int k = kb; k < ke; ++k) {
     float2 X[16];
 #pragma unroll
@@ -350,8 +548,8 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) Z[own<T>(jbase, j, q)] = 0ull;
       __builtin_amdgcn_wave_barrier();
-      if (f1 == 0) fold_all<G, kU, true>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
-      else fold_all<G, kU, false>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      if (f1 == 0) fold_all<G, kU, kFoldRow0, C / 2>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      else fold_all<G, kU, kFoldRow, C / 2>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
       // first batch of the next (side, k), in flight during the transform
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
       else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0, own_off);
@@ -388,16 +586,40 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   for (int q = 0; q < 16; ++q) out[j + T * q] = acc[q];
 }
 
+// The pair kernel has one block per (repetition, k-split), an eighth of the
+// work at R = 16; alone it would leave most of the chip idle for its last
+// blocks, so with `ov` it runs on the second stream beside the row kernel.
 template <int L>
-static hipError_t launch_L(const FftArgs& a, hipStream_t s) {
+static hipError_t launch_L(FftArgs a, const Geometry& g, hipStream_t s, const Overlap* ov) {
   typedef FftShape<L> F;
   const size_t lds = (size_t)(2 * F::C + F::NMID + 16 * a.R) * sizeof(float2);
-  hipLaunchKernelGGL(k_fft_mac<L>, dim3(a.nwg), dim3(F::T), lds, s, a);
-  return hipGetLastError();
+  hipError_t e = hipSuccess;
+  const bool fork = ov && g.R > 1;
+  if (fork) {
+    if ((e = hipEventRecord(ov->fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(ov->aux, ov->fork, 0)) != hipSuccess) return e;
+  }
+  if (g.R > 1) {
+    a.nwg = g.d * g.KS;
+    a.remap = (a.nwg % 8 == 0) ? 1 : 0;
+    hipLaunchKernelGGL(k_fft_mac_pair<L>, dim3(a.nwg), dim3(F::T), lds, fork ? ov->aux : s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (fork && (e = hipEventRecord(ov->join, ov->aux)) != hipSuccess) return e;
+  a.nrow = g.R > 1 ? g.R / 2 - 1 : 1;
+  a.roff = g.R > 1 ? 1 : 0;
+  if (a.nrow > 0) {
+    a.nwg = g.d * g.KS * a.nrow;
+    a.remap = (a.nwg % 8 == 0) ? 1 : 0;
+    hipLaunchKernelGGL(k_fft_mac<L>, dim3(a.nwg), dim3(F::T), lds, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (fork) e = hipStreamWaitEvent(s, ov->join, 0);
+  return e;
 }
 
 hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc& sb,
-                          const float2* tw32, float2* Ppart, hipStream_t s) {
+                          const float2* tw32, float2* Ppart, hipStream_t s, const Overlap* ov) {
   FftArgs a;
   a.SA0 = sa.SA; a.SA1 = sb.SA;
   a.ent0 = sa.ent; a.ent1 = sb.ent;
@@ -406,19 +628,18 @@ hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc&
   a.Lcap0 = sa.Lcap; a.Lcap1 = sb.Lcap; a.Lrow0 = sa.Lrow; a.Lrow1 = sb.Lrow;
   a.tw = tw32; a.Ppart = Ppart; a.b = g.b;
   a.R = g.R; a.rows = g.rows; a.d = g.d; a.m = g.m; a.KS = g.KS;
-  a.nwg = g.d * g.KS * g.rows;
-  a.remap = (a.nwg % 8 == 0) ? 1 : 0;
+  a.nrow = 1; a.roff = 0; a.nwg = 0; a.remap = 0;
   switch (g.log2c) {
-    case 4: return launch_L<4>(a, s);
-    case 5: return launch_L<5>(a, s);
-    case 6: return launch_L<6>(a, s);
-    case 7: return launch_L<7>(a, s);
-    case 8: return launch_L<8>(a, s);
-    case 9: return launch_L<9>(a, s);
-    case 10: return launch_L<10>(a, s);
-    case 11: return launch_L<11>(a, s);
-    case 12: return launch_L<12>(a, s);
-    case 13: return launch_L<13>(a, s);
+    case 4: return launch_L<4>(a, g, s, ov);
+    case 5: return launch_L<5>(a, g, s, ov);
+    case 6: return launch_L<6>(a, g, s, ov);
+    case 7: return launch_L<7>(a, g, s, ov);
+    case 8: return launch_L<8>(a, g, s, ov);
+    case 9: return launch_L<9>(a, g, s, ov);
+    case 10: return launch_L<10>(a, g, s, ov);
+    case 11: return launch_L<11>(a, g, s, ov);
+    case 12: return launch_L<12>(a, g, s, ov);
+    case 13: return launch_L<13>(a, g, s, ov);
     default: return hipErrorInvalidValue;
   }
 }
@@ -426,11 +647,14 @@ hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc&
 // Raise the dynamic LDS limit of every row length to 160 KB (done once per
 // context, outside any graph capture).
 hipError_t prepare_fft_mac() {
-  const void* fns[] = {reinterpret_cast<const void*>(&k_fft_mac<4>), reinterpret_cast<const void*>(&k_fft_mac<5>),
-                       reinterpret_cast<const void*>(&k_fft_mac<6>), reinterpret_cast<const void*>(&k_fft_mac<7>),
-                       reinterpret_cast<const void*>(&k_fft_mac<8>), reinterpret_cast<const void*>(&k_fft_mac<9>),
-                       reinterpret_cast<const void*>(&k_fft_mac<10>), reinterpret_cast<const void*>(&k_fft_mac<11>),
-                       reinterpret_cast<const void*>(&k_fft_mac<12>), reinterpret_cast<const void*>(&k_fft_mac<13>)};
+#define CMM_FNS(K) \
+  reinterpret_cast<const void*>(&K<4>), reinterpret_cast<const void*>(&K<5>), \
+  reinterpret_cast<const void*>(&K<6>), reinterpret_cast<const void*>(&K<7>), \
+  reinterpret_cast<const void*>(&K<8>), reinterpret_cast<const void*>(&K<9>), \
+  reinterpret_cast<const void*>(&K<10>), reinterpret_cast<const void*>(&K<11>), \
+  reinterpret_cast<const void*>(&K<12>), reinterpret_cast<const void*>(&K<13>)
+  const void* fns[] = {CMM_FNS(k_fft_mac), CMM_FNS(k_fft_mac_pair)};
+#undef CMM_FNS
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
