@@ -71,6 +71,8 @@ def parse():
     p.add_argument("--no-sparse", action="store_true", help="skip the sparse-operand measurement")
     p.add_argument("--no-autotune", action="store_true",
                    help="use the built-in geometry instead of tuning the size class first")
+    p.add_argument("--geometry", type=str, default=None,
+                   help="log2c,kmax,cs_blocks: run the headline with this geometry instead of tuning")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -340,10 +342,11 @@ def run_extract(ctx, w, median_x2):
     return res
 
 
-def traffic_record(w):
-    """HBM bytes per fft_mac launch from the committed rocprofv3 counter
-    summary, if it was taken on this workload and the kernel source has not
-    changed since (else None)."""
+def traffic_record(w, geometry):
+    """HBM bytes per spectral step (both fft_mac kernels) from the committed
+    rocprofv3 counter summary, if it was taken on this workload at this
+    geometry (log2c, kmax, cs_blocks) and the kernel source has not changed
+    since (else None)."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", "fft_mac_cov4096_f32_traffic.json")
     src = os.path.join(ROOT, "paper_1108_1320_amd", "csrc", "k_fft_mac.hip")
@@ -352,7 +355,10 @@ def traffic_record(w):
     rec = json.load(open(rec_path))
     if rec.get("source_sha256_16") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
         return None
-    return rec["read_bytes"] + rec["write_bytes"]
+    for r in rec.get("records", []):
+        if list(r["geometry"]) == list(geometry):
+            return r["read_bytes"] + r["write_bytes"]
+    return None
 
 
 def planted_recall(w, oi, oj):
@@ -397,7 +403,9 @@ def main():
     n1, m, n3, b, d, K = w.n1, w.m, w.n3, w.b, w.d, w.K
     ctx = cmm.Context(0)
     tuned = None
-    if not args.no_autotune:
+    if args.geometry:
+        ctx.set_tuning(n1, m, n3, b, d, w.dtype, tuple(int(x) for x in args.geometry.split(",")))
+    elif not args.no_autotune:
         # the library's one-time tuning of this size class (cached in the context)
         t0 = time.perf_counter()
         tu, tms = ctx.autotune(n1, m, n3, b, d, w.dtype)
@@ -452,7 +460,7 @@ def main():
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": traffic_record(w),
+            "traffic": traffic_record(w, ctx.tuning(n1, m, n3, b, d, w.dtype)),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flop_per_launch": flop,
             "avg_launch_ms": round(fft_avg_ms, 4),

@@ -39,10 +39,21 @@ def test_expected_nonempty_matches_simulation():
 
 
 def test_traffic_record_only_for_its_workload():
-    w = W.make_workload(1)
-    assert bench.traffic_record(w) is None          # recorded for covariance 4096 f32 only
+    import json
     rec = os.path.join(ROOT, "profiles", "fft_mac_cov4096_f32_traffic.json")
     assert os.path.exists(rec)
+    geos = [tuple(r["geometry"]) for r in json.load(open(rec))["records"]]
+    assert geos
+    w = W.make_workload(1)
+    assert bench.traffic_record(w, geos[0]) is None  # recorded for covariance 4096 f32 only
+    w2 = W.make_workload(2)
+    assert bench.traffic_record(w2, (9, 7, 5)) is None  # no record at another geometry
+    import hashlib
+    src = os.path.join(ROOT, "paper_1108_1320_amd", "csrc", "k_fft_mac.hip")
+    fresh = json.load(open(rec))["source_sha256_16"] == hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for g in geos:              # present for each recorded geometry while the source is unchanged
+        t = bench.traffic_record(w2, g)
+        assert (t > 0) if fresh else (t is None)
 
 
 def test_multi_gpu_request_refused():
