@@ -240,6 +240,19 @@ int cmm_batch_run(cmm_batch* batch, uint32_t flags);
  * replay; cmm_sketch_free() on it returns CMM_ESTATE. */
 int cmm_batch_sketch(cmm_batch* batch, int32_t index, cmm_sketch** out);
 
+/* cmm_topk of every product of the batch, on the context stream, with
+ * K[q] for product q (an array of the batch's count) and one `mode` for all.
+ * Product q's results start at offset sum over p < q of K[p] (K[p]*n3 of
+ * product p for CMM_TOPK_PER_COLUMN) in the host arrays out_i, out_j and
+ * out_val, which hold the total.  Results equal those of cmm_topk on each
+ * product's sketch; each decoding phase is issued for all products before
+ * its one host wait (DECOMPRESS, Figure 1; the selection itself is this
+ * library's, see cmm_topk).  Errors as cmm_topk's, checked for every product
+ * before any work starts, except CMM_EUNSUPPORTED for more than 4096 tied
+ * estimates, which can come after earlier products' work. */
+int cmm_batch_topk(cmm_batch* batch, const int32_t* K, int32_t mode, int64_t* out_i, int64_t* out_j,
+                   float* out_val);
+
 /* Wait for the context stream and release the graph, the workspace and the
  * batch's sketches. */
 int cmm_batch_free(cmm_batch* batch);

@@ -72,6 +72,7 @@ _SIGS = {
     "cmm_batch_create": (C.c_int, [_P, _PROB, _I32, _U32, C.POINTER(_P)]),
     "cmm_batch_run": (C.c_int, [_P, _U32]),
     "cmm_batch_sketch": (C.c_int, [_P, _I32, C.POINTER(_P)]),
+    "cmm_batch_topk": (C.c_int, [_P, _I32P, _I32, _P, _P, _P]),
     "cmm_batch_free": (C.c_int, [_P]),
     "cmm_sketch_product_batched": (C.c_int, [_P, _PROB, _I32, C.POINTER(_P)]),
     "cmm_autotune": (C.c_int, [_P, _I64, _I64, _I64, _I64, _I32, _I32, _I32P,
@@ -289,6 +290,22 @@ def cmm_batch_run(batch, flags=0, ctx=None):
 def cmm_batch_sketch(batch, index: int):
     out = _P()
     _check(load().cmm_batch_sketch(batch, index, C.byref(out)), "cmm_batch_sketch")
+    return out
+
+
+def cmm_batch_topk(batch, Ks, mode: int, sizes):
+    """cmm_batch_topk with K[q] = Ks[q]; `sizes` are the products' (n1, n3).
+    Returns one (i, j, val) triple of host arrays per product."""
+    Ks = np.ascontiguousarray(Ks, dtype=np.int32)
+    cnt = [int(k) * (n3 if mode == CMM_TOPK_PER_COLUMN else 1) for k, (n1, n3) in zip(Ks, sizes)]
+    tot = max(1, sum(cnt))
+    oi = np.empty(tot, np.int64); oj = np.empty(tot, np.int64); ov = np.empty(tot, np.float32)
+    _check(load().cmm_batch_topk(batch, Ks.ctypes.data_as(_I32P), mode, oi.ctypes.data_as(_P),
+                                 oj.ctypes.data_as(_P), ov.ctypes.data_as(_P)), "cmm_batch_topk")
+    out, off = [], 0
+    for c in cnt:
+        out.append((oi[off:off + c], oj[off:off + c], ov[off:off + c]))
+        off += c
     return out
 
 
@@ -512,6 +529,20 @@ class Batch:
 
     def sketch(self, index: int) -> Sketch:
         return Sketch(cmm_batch_sketch(self.handle, index), self.ctx, owner=self)
+
+    def topk(self, Ks, mode="all"):
+        """Top-K of every product (Ks: one K per product, or one int for all);
+        the host waits of all products are shared.  Returns a list of
+        (i, j, val) per product."""
+        if isinstance(Ks, int):
+            Ks = [Ks] * self.count
+        if len(Ks) != self.count:
+            raise ValueError("one K per product")
+        sizes = []
+        for q in range(self.count):
+            n1, m, n3, b, d = cmm_sketch_info(cmm_batch_sketch(self.handle, q))
+            sizes.append((n1, n3))
+        return cmm_batch_topk(self.handle, Ks, MODES[mode] if isinstance(mode, str) else mode, sizes)
 
     def free(self):
         if self.handle:

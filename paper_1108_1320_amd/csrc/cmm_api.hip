@@ -53,7 +53,8 @@ struct cmm_ctx {
   std::vector<Pending> pending;
   std::map<std::string, std::pair<double, int64_t>> prof_acc;
   uint32_t* pinned_u32 = nullptr;   // small pinned host scratch
-  char* pinned = nullptr;           // pinned staging of small downloads (kPinnedBytes)
+  char* pinned = nullptr;           // pinned staging of downloads (pinned_cap bytes)
+  size_t pinned_cap = 0;
   std::map<TuneKey, TuneEntry> tuning;
   std::string arch;
   int64_t ws_limit = 0;     // workspace limit of one product in bytes (0: ws_default)
@@ -90,7 +91,8 @@ int fail(cmm_ctx* c, int code, const std::string& msg) {
   return code;
 }
 
-constexpr size_t kPinnedBytes = 256 * 1024;
+constexpr size_t kPinnedBytes = 256 * 1024;   // initial pinned staging
+constexpr size_t kPinnedMax = 64u << 20;       // the staging grows up to this
 
 #define CMM_HIP(ctx, expr)                                                          \
   do {                                                                              \
@@ -110,6 +112,7 @@ struct Download {
 // together go through the context's pinned buffer instead (plain DMA) and
 // are moved to their destinations on the host.
 int download(cmm_ctx* c, hipStream_t s, std::initializer_list<Download> list);
+int download_n(cmm_ctx* c, hipStream_t s, const Download* list, size_t n);
 
 bool valid_ctx(const cmm_ctx* c) { return c && c->magic == kCtxMagic; }
 bool valid_sketch(const cmm_sketch* s) { return s && s->magic == kSketchMagic && valid_ctx(s->ctx); }
@@ -422,12 +425,26 @@ int enqueue_layout(cmm_ctx* c, const cmm::Geometry& g, cmm::SideDesc side[2],
 // Every kernel of one sketch product, in stream order, on stream `s`: no
 // allocation, no host synchronisation, no host-to-device copy (hash
 // parameters are already at `pdev`), so the sequence can be captured.
-int download(cmm_ctx* c, hipStream_t s, std::initializer_list<Download> list) {
+// Grow the pinned staging buffer to `bytes` (at most kPinnedMax; the old
+// buffer is idle between calls, every download waits before returning).
+bool ensure_pinned(cmm_ctx* c, size_t bytes) {
+  if (c->pinned && bytes <= c->pinned_cap) return true;
+  if (bytes > kPinnedMax) return false;
+  char* p = nullptr;
+  if (hipHostMalloc((void**)&p, bytes) != hipSuccess) { (void)hipGetLastError(); return false; }
+  if (c->pinned) hipHostFree(c->pinned);
+  c->pinned = p;
+  c->pinned_cap = bytes;
+  return true;
+}
+
+int download_n(cmm_ctx* c, hipStream_t s, const Download* list, size_t n) {
   size_t total = 0;
-  for (const Download& x : list) total += (x.bytes + 255) & ~(size_t)255;
-  const bool staged = c->pinned && total <= kPinnedBytes;
+  for (size_t q = 0; q < n; ++q) total += (list[q].bytes + 255) & ~(size_t)255;
+  const bool staged = ensure_pinned(c, total);
   size_t off = 0;
-  for (const Download& x : list) {
+  for (size_t q = 0; q < n; ++q) {
+    const Download& x = list[q];
     if (x.bytes == 0) continue;
     void* to = staged ? (void*)(c->pinned + off) : x.dst;
     CMM_HIP(c, hipMemcpyAsync(to, x.src, x.bytes, hipMemcpyDeviceToHost, s));
@@ -436,13 +453,18 @@ int download(cmm_ctx* c, hipStream_t s, std::initializer_list<Download> list) {
   CMM_HIP(c, hipStreamSynchronize(s));
   if (staged) {
     off = 0;
-    for (const Download& x : list) {
+    for (size_t q = 0; q < n; ++q) {
+      const Download& x = list[q];
       if (x.bytes == 0) continue;
       std::memcpy(x.dst, c->pinned + off, x.bytes);
       off += (x.bytes + 255) & ~(size_t)255;
     }
   }
   return CMM_OK;
+}
+
+int download(cmm_ctx* c, hipStream_t s, std::initializer_list<Download> list) {
+  return download_n(c, s, list.begin(), list.size());
 }
 
 // All kernels of one product on stream `s`.  The float64 sketch goes to
@@ -1033,6 +1055,202 @@ cmm::DecodeDesc decode_desc(const cmm_sketch* sk) {
   return dd;
 }
 
+// One request of topk_many: a sketch, its K and host destinations.
+struct TopkJob {
+  const cmm_sketch* sk;
+  int32_t K;
+  int64_t* out_i;
+  int64_t* out_j;
+  float* out_val;
+};
+
+// Top-K (cmm_topk's semantics) of several sketches of context `c`, on its
+// stream.  Each phase is issued for every sketch before the single host wait
+// it needs, so n sketches cost the round trips of one; a sketch whose fast
+// path does not settle runs the digit passes with waits of its own.
+int topk_many(cmm_ctx* c, int mode, const std::vector<TopkJob>& jobs) {
+  if (mode != CMM_TOPK_ALL && mode != CMM_TOPK_UPPER && mode != CMM_TOPK_PER_COLUMN)
+    return fail(c, CMM_EINVAL, "unknown mode");
+  const size_t n = jobs.size();
+  std::vector<int64_t> domain(n, 0);
+  for (size_t q = 0; q < n; ++q) {
+    const TopkJob& jb = jobs[q];
+    const cmm_sketch* sk = jb.sk;
+    if (!jb.out_i || !jb.out_j || !jb.out_val) return fail(c, CMM_EINVAL, "output arrays are NULL");
+    if (jb.K < 1) return fail(c, CMM_EINVAL, "K < 1");
+    if (mode == CMM_TOPK_PER_COLUMN) {
+      if (jb.K > sk->n1) return fail(c, CMM_EINVAL, "K larger than a column");
+      continue;
+    }
+    int64_t dom = sk->n1 * sk->n3;
+    if (mode == CMM_TOPK_UPPER) {
+      dom = 0;
+      for (int64_t i = 0; i < sk->n1; ++i) dom += std::max<int64_t>(0, sk->n3 - i - 1);
+    }
+    domain[q] = dom;
+    if (jb.K > dom) return fail(c, CMM_EINVAL, "K larger than the candidate domain");
+    if (jb.K > cmm::kTopkCap / 2) return fail(c, CMM_EUNSUPPORTED, "K above 2048");
+  }
+  hipStream_t s = c->stream;
+  Work w(c);
+  std::vector<Download> dl;
+  if (mode == CMM_TOPK_PER_COLUMN) {
+    {
+      Scope sc_(c, "decode");
+      for (size_t q = 0; q < n; ++q) {
+        const TopkJob& jb = jobs[q];
+        const size_t tot = (size_t)jb.K * jb.sk->n3;
+        int64_t* oi = w.get<int64_t>(tot);
+        float* ov = w.get<float>(tot);
+        if (!oi || !ov) return fail(c, CMM_ENOMEM, "workspace allocation failed");
+        CMM_HIP(c, cmm::launch_topk_column(decode_desc(jb.sk), jb.K, oi, ov, s));
+        dl.push_back({jb.out_i, oi, sizeof(int64_t) * tot});
+        dl.push_back({jb.out_val, ov, sizeof(float) * tot});
+      }
+    }
+    const int rc = download_n(c, s, dl.data(), dl.size());
+    if (rc) return rc;
+    for (const TopkJob& jb : jobs)
+      for (int64_t jj = 0; jj < jb.sk->n3; ++jj)
+        for (int r = 0; r < jb.K; ++r) jb.out_j[jj * jb.K + r] = jj;
+    return CMM_OK;
+  }
+  constexpr int kWide = 16384;   // candidates kept by the fused histogram + collect pass
+  struct State {
+    cmm::DecodeDesc dd;
+    int tiles = 0, b0 = -1;
+    bool done = false;
+    uint32_t* hist = nullptr;
+    uint32_t* count = nullptr;
+    cmm::TopkCand* wide = nullptr;
+    cmm::TopkCand* cand = nullptr;
+    int64_t* oi = nullptr;
+    int64_t* oj = nullptr;
+    float* ov = nullptr;
+    std::vector<uint32_t> h;
+  };
+  std::vector<State> st(n);
+  for (size_t q = 0; q < n; ++q) {
+    State& x = st[q];
+    const TopkJob& jb = jobs[q];
+    x.dd = decode_desc(jb.sk);
+    x.tiles = (int)((jb.sk->n1 + 15) / 16);
+    x.hist = w.get<uint32_t>(4096);
+    x.count = w.get<uint32_t>(2);
+    x.wide = w.get<cmm::TopkCand>(kWide);
+    x.cand = w.get<cmm::TopkCand>(cmm::kTopkCap);
+    x.oi = w.get<int64_t>(jb.K);
+    x.oj = w.get<int64_t>(jb.K);
+    x.ov = w.get<float>(jb.K);
+    if (!x.hist || !x.count || !x.wide || !x.cand || !x.oi || !x.oj || !x.ov)
+      return fail(c, CMM_ENOMEM, "workspace allocation failed");
+    x.h.assign(4096, 0u);
+  }
+  {
+    Scope sc_(c, "decode");
+    // Fast path: a pass over every 16th row tile estimates a threshold T0
+    // above which about 2K + 64 estimates lie; one full pass then builds the
+    // exact histogram of the top 12 key bits of the keys >= T0 and keeps
+    // those candidates.  The histogram shows whether T0 is at or below the
+    // K-th key and whether the kept set is complete; otherwise the
+    // digit-by-digit passes below run.
+    dl.clear();
+    for (State& x : st) {
+      if (x.tiles < 64) continue;
+      CMM_HIP(c, cmm::launch_fill_i32((int32_t*)x.hist, 4096, 0, s));
+      CMM_HIP(c, cmm::launch_topk_hist(x.dd, mode, 16, 0, 32, 19, 0xFFF, x.hist, 0, nullptr, nullptr, 0, s));
+      dl.push_back({x.h.data(), x.hist, 4096 * sizeof(uint32_t)});
+    }
+    if (!dl.empty()) { const int rc_ = download_n(c, s, dl.data(), dl.size()); if (rc_) return rc_; }
+    dl.clear();
+    for (size_t q = 0; q < n; ++q) {
+      State& x = st[q];
+      if (x.tiles < 64) continue;
+      int64_t sampled = 0;
+      for (uint32_t v : x.h) sampled += v;
+      if (sampled <= 0) continue;
+      const double want = (2.0 * jobs[q].K + 64.0) * (double)sampled / (double)domain[q];
+      int64_t cum = 0;
+      for (int b = 4095; b >= 0; --b) {
+        cum += x.h[b];
+        if (cum >= 8 && (double)cum >= want) { x.b0 = b; break; }
+      }
+      if (x.b0 < 0) continue;
+      const uint32_t T0 = (uint32_t)x.b0 << 19;
+      CMM_HIP(c, cmm::launch_fill_i32((int32_t*)x.hist, 4096, 0, s));
+      CMM_HIP(c, cmm::launch_fill_i32((int32_t*)x.count, 2, 0, s));
+      CMM_HIP(c, cmm::launch_topk_hist(x.dd, mode, 1, 0, 32, 19, 0xFFF, x.hist, T0, x.wide, x.count, kWide, s));
+      dl.push_back({x.h.data(), x.hist, 4096 * sizeof(uint32_t)});
+    }
+    if (!dl.empty()) { const int rc_ = download_n(c, s, dl.data(), dl.size()); if (rc_) return rc_; }
+    for (size_t q = 0; q < n; ++q) {
+      State& x = st[q];
+      if (x.b0 < 0) continue;
+      const int K = jobs[q].K;
+      // h counts only keys >= T0 (bins b0 and up): exact there
+      int64_t n0 = 0;
+      for (int b = x.b0; b < 4096; ++b) n0 += x.h[b];
+      if (n0 < K || n0 > kWide) continue;
+      int64_t cum = 0;
+      int bk = 4095;
+      for (; bk >= 0; --bk) { cum += x.h[bk]; if (cum >= K) break; }
+      if (n0 <= cmm::kTopkCap) {
+        CMM_HIP(c, cmm::launch_topk_final(x.wide, x.count, cmm::kTopkCap, K, x.dd.n3, x.oi, x.oj, x.ov, s));
+        x.done = true;
+      } else if (cum <= cmm::kTopkCap) {
+        CMM_HIP(c, cmm::launch_topk_filter(x.wide, x.count, kWide, (uint32_t)bk << 19, x.cand, x.count + 1,
+                                           cmm::kTopkCap, s));
+        CMM_HIP(c, cmm::launch_topk_final(x.cand, x.count + 1, cmm::kTopkCap, K, x.dd.n3, x.oi, x.oj, x.ov, s));
+        x.done = true;
+      }
+    }
+    for (size_t q = 0; q < n; ++q) {
+      State& x = st[q];
+      if (x.done) continue;
+      // digit passes: bits [30:19], [18:7], [6:0]
+      const int dshift[3] = {19, 7, 0};
+      const uint32_t dmask[3] = {0xFFF, 0xFFF, 0x7F};
+      uint32_t prefix = 0;
+      int pshift = 32;
+      int64_t above = 0;
+      int64_t need = jobs[q].K;
+      uint32_t thresh = 0;
+      bool found = false;
+      for (int level = 0; level < 3 && !found; ++level) {
+        CMM_HIP(c, cmm::launch_fill_i32((int32_t*)x.hist, 4096, 0, s));
+        CMM_HIP(c, cmm::launch_topk_hist(x.dd, mode, 1, prefix, pshift, dshift[level], dmask[level], x.hist,
+                                         0, nullptr, nullptr, 0, s));
+        { const int rc_ = download(c, s, {{x.h.data(), x.hist, 4096 * sizeof(uint32_t)}}); if (rc_) return rc_; }
+        int64_t cum = 0;
+        int bin = -1;
+        for (int b = (int)dmask[level]; b >= 0; --b) {
+          if (cum + x.h[b] >= need) { bin = b; break; }
+          cum += x.h[b];
+        }
+        if (bin < 0) return fail(c, CMM_EHIP, "top-K histogram lost entries");
+        prefix |= (uint32_t)bin << dshift[level];
+        const int64_t total = above + cum + x.h[bin];
+        if (total <= cmm::kTopkCap) { thresh = prefix; found = true; break; }
+        above += cum;
+        need -= cum;
+        pshift = dshift[level];
+      }
+      if (!found) return fail(c, CMM_EUNSUPPORTED, "more than 4096 estimates tie at the K-th magnitude");
+      CMM_HIP(c, cmm::launch_fill_i32((int32_t*)x.count, 1, 0, s));
+      CMM_HIP(c, cmm::launch_topk_collect(x.dd, mode, thresh, x.cand, x.count, cmm::kTopkCap, s));
+      CMM_HIP(c, cmm::launch_topk_final(x.cand, x.count, cmm::kTopkCap, jobs[q].K, x.dd.n3, x.oi, x.oj, x.ov, s));
+    }
+  }
+  dl.clear();
+  for (size_t q = 0; q < n; ++q) {
+    const TopkJob& jb = jobs[q];
+    dl.push_back({jb.out_i, st[q].oi, sizeof(int64_t) * jb.K});
+    dl.push_back({jb.out_j, st[q].oj, sizeof(int64_t) * jb.K});
+    dl.push_back({jb.out_val, st[q].ov, sizeof(float) * jb.K});
+  }
+  return download_n(c, s, dl.data(), dl.size());
+}
+
 }  // namespace
 
 // =========================================================================
@@ -1071,6 +1289,7 @@ int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out) {
     delete c;
     return CMM_ENOMEM;
   }
+  c->pinned_cap = kPinnedBytes;
   size_t mem_free = 0, mem_total = 0;
   c->ws_default = hipMemGetInfo(&mem_free, &mem_total) == hipSuccess && mem_total > 0
                       ? (int64_t)(mem_total / 2) : (int64_t)64 << 30;
@@ -1281,132 +1500,7 @@ int cmm_estimate_batch(const cmm_sketch* sk, const int64_t* i, const int64_t* j,
 int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int64_t* out_j,
              float* out_val) {
   if (!valid_sketch(sk)) return CMM_EINVAL;
-  cmm_ctx* c = sk->ctx;
-  if (!out_i || !out_j || !out_val) return fail(c, CMM_EINVAL, "output arrays are NULL");
-  if (K < 1) return fail(c, CMM_EINVAL, "K < 1");
-  hipStream_t s = c->stream;
-  const cmm::DecodeDesc dd = decode_desc(sk);
-  Work w(c);
-  if (mode == CMM_TOPK_PER_COLUMN) {
-    if (K > sk->n1) return fail(c, CMM_EINVAL, "K larger than a column");
-    const size_t tot = (size_t)K * sk->n3;
-    int64_t* oi = w.get<int64_t>(tot);
-    float* ov = w.get<float>(tot);
-    if (!oi || !ov) return fail(c, CMM_ENOMEM, "workspace allocation failed");
-    {
-      Scope sc_(c, "decode");
-      CMM_HIP(c, cmm::launch_topk_column(dd, K, oi, ov, s));
-    }
-    const int rc = download(c, s, {{out_i, oi, sizeof(int64_t) * tot}, {out_val, ov, sizeof(float) * tot}});
-    if (rc) return rc;
-    for (int64_t jj = 0; jj < sk->n3; ++jj)
-      for (int r = 0; r < K; ++r) out_j[jj * K + r] = jj;
-    return CMM_OK;
-  }
-  if (mode != CMM_TOPK_ALL && mode != CMM_TOPK_UPPER) return fail(c, CMM_EINVAL, "unknown mode");
-  const int64_t domain = mode == CMM_TOPK_ALL
-                             ? sk->n1 * sk->n3
-                             : [&] { int64_t t = 0; for (int64_t i = 0; i < sk->n1; ++i) t += std::max<int64_t>(0, sk->n3 - i - 1); return t; }();
-  if (K > domain) return fail(c, CMM_EINVAL, "K larger than the candidate domain");
-  if (K > cmm::kTopkCap / 2) return fail(c, CMM_EUNSUPPORTED, "K above 2048");
-  constexpr int kWide = 16384;   // candidates kept by the fused histogram + collect pass
-  uint32_t* hist = w.get<uint32_t>(4096);
-  uint32_t* count = w.get<uint32_t>(2);
-  cmm::TopkCand* wide = w.get<cmm::TopkCand>(kWide);
-  cmm::TopkCand* cand = w.get<cmm::TopkCand>(cmm::kTopkCap);
-  int64_t* oi = w.get<int64_t>(K);
-  int64_t* oj = w.get<int64_t>(K);
-  float* ov = w.get<float>(K);
-  if (!hist || !count || !wide || !cand || !oi || !oj || !ov)
-    return fail(c, CMM_ENOMEM, "workspace allocation failed");
-  std::vector<uint32_t> h(4096);
-  const int tiles = (int)((sk->n1 + 15) / 16);
-  {
-    Scope sc_(c, "decode");
-    // Fast path: a pass over every 16th row tile estimates a threshold T0
-    // above which about 2K + 64 estimates lie; one full pass then builds the
-    // exact histogram of the top 12 key bits of the keys >= T0 and keeps
-    // those candidates.  The histogram shows whether T0 is at or below the
-    // K-th key and whether the kept set is complete; otherwise the
-    // digit-by-digit passes below run.
-    bool done = false;
-    if (tiles >= 64) {
-      CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
-      CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 16, 0, 32, 19, 0xFFF, hist, 0, nullptr, nullptr, 0, s));
-      { const int rc_ = download(c, s, {{h.data(), hist, 4096 * sizeof(uint32_t)}}); if (rc_) return rc_; }
-      int64_t sampled = 0;
-      for (uint32_t x : h) sampled += x;
-      int b0 = -1;
-      if (sampled > 0) {
-        const double want = (2.0 * K + 64.0) * (double)sampled / (double)domain;
-        int64_t cum = 0;
-        for (int q = 4095; q >= 0; --q) {
-          cum += h[q];
-          if (cum >= 8 && (double)cum >= want) { b0 = q; break; }
-        }
-      }
-      if (b0 >= 0) {
-        const uint32_t T0 = (uint32_t)b0 << 19;
-        CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
-        CMM_HIP(c, cmm::launch_fill_i32((int32_t*)count, 2, 0, s));
-        CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 1, 0, 32, 19, 0xFFF, hist, T0, wide, count, kWide, s));
-        { const int rc_ = download(c, s, {{h.data(), hist, 4096 * sizeof(uint32_t)}}); if (rc_) return rc_; }
-        // h counts only keys >= T0 (bins b0 and up): exact there
-        int64_t n0 = 0;
-        for (int q = b0; q < 4096; ++q) n0 += h[q];
-        if (n0 >= K && n0 <= kWide) {
-          int64_t cum = 0;
-          int bk = 4095;
-          for (; bk >= 0; --bk) { cum += h[bk]; if (cum >= K) break; }
-          if (n0 <= cmm::kTopkCap) {
-            CMM_HIP(c, cmm::launch_topk_final(wide, count, cmm::kTopkCap, K, (int)sk->n3, oi, oj, ov, s));
-            done = true;
-          } else if (cum <= cmm::kTopkCap) {
-            CMM_HIP(c, cmm::launch_topk_filter(wide, count, kWide, (uint32_t)bk << 19, cand, count + 1,
-                                               cmm::kTopkCap, s));
-            CMM_HIP(c, cmm::launch_topk_final(cand, count + 1, cmm::kTopkCap, K, (int)sk->n3, oi, oj, ov, s));
-            done = true;
-          }
-        }
-      }
-    }
-    if (!done) {
-      // digit passes: bits [30:19], [18:7], [6:0]
-      const int dshift[3] = {19, 7, 0};
-      const uint32_t dmask[3] = {0xFFF, 0xFFF, 0x7F};
-      uint32_t prefix = 0;
-      int pshift = 32;
-      int64_t above = 0;
-      int64_t need = K;
-      uint32_t thresh = 0;
-      bool found = false;
-      for (int level = 0; level < 3 && !found; ++level) {
-        CMM_HIP(c, cmm::launch_fill_i32((int32_t*)hist, 4096, 0, s));
-        CMM_HIP(c, cmm::launch_topk_hist(dd, mode, 1, prefix, pshift, dshift[level], dmask[level], hist,
-                                         0, nullptr, nullptr, 0, s));
-        { const int rc_ = download(c, s, {{h.data(), hist, 4096 * sizeof(uint32_t)}}); if (rc_) return rc_; }
-        int64_t cum = 0;
-        int bin = -1;
-        for (int q = (int)dmask[level]; q >= 0; --q) {
-          if (cum + h[q] >= need) { bin = q; break; }
-          cum += h[q];
-        }
-        if (bin < 0) return fail(c, CMM_EHIP, "top-K histogram lost entries");
-        prefix |= (uint32_t)bin << dshift[level];
-        const int64_t total = above + cum + h[bin];
-        if (total <= cmm::kTopkCap) { thresh = prefix; found = true; break; }
-        above += cum;
-        need -= cum;
-        pshift = dshift[level];
-      }
-      if (!found) return fail(c, CMM_EUNSUPPORTED, "more than 4096 estimates tie at the K-th magnitude");
-      CMM_HIP(c, cmm::launch_fill_i32((int32_t*)count, 1, 0, s));
-      CMM_HIP(c, cmm::launch_topk_collect(dd, mode, thresh, cand, count, cmm::kTopkCap, s));
-      CMM_HIP(c, cmm::launch_topk_final(cand, count, cmm::kTopkCap, K, (int)sk->n3, oi, oj, ov, s));
-    }
-  }
-  return download(c, s, {{out_i, oi, sizeof(int64_t) * K}, {out_j, oj, sizeof(int64_t) * K},
-                         {out_val, ov, sizeof(float) * K}});
+  return topk_many(sk->ctx, mode, {TopkJob{sk, K, out_i, out_j, out_val}});
 }
 
 int cmm_batch_create(cmm_ctx* ctx, const cmm_problem* probs, int32_t count, uint32_t flags,
@@ -1461,6 +1555,30 @@ int cmm_batch_sketch(cmm_batch* batch, int32_t index, cmm_sketch** out) {
   if (!out) return fail(batch->ctx, CMM_EINVAL, "out is NULL");
   if (index < 0 || index >= (int32_t)batch->sk.size()) return fail(batch->ctx, CMM_EINVAL, "index out of range");
   *out = batch->sk[index];
+  return CMM_OK;
+}
+
+int cmm_batch_topk(cmm_batch* batch, const int32_t* K, int32_t mode, int64_t* out_i, int64_t* out_j,
+                   float* out_val) {
+  if (!valid_batch(batch)) return CMM_EINVAL;
+  cmm_ctx* c = batch->ctx;
+  if (!K || !out_i || !out_j || !out_val) return fail(c, CMM_EINVAL, "K or an output array is NULL");
+  CMM_HIP(c, hipSetDevice(c->device));
+  // the workspace of a group is about 0.35 MB per product
+  constexpr size_t kGroup = 256;
+  std::vector<TopkJob> jobs;
+  int64_t off = 0;
+  for (size_t q = 0; q < batch->sk.size(); ++q) {
+    const cmm_sketch* sk = batch->sk[q];
+    if (K[q] < 1) return fail(c, CMM_EINVAL, "K < 1");
+    jobs.push_back(TopkJob{sk, K[q], out_i + off, out_j + off, out_val + off});
+    off += mode == CMM_TOPK_PER_COLUMN ? (int64_t)K[q] * sk->n3 : (int64_t)K[q];
+  }
+  for (size_t g = 0; g < jobs.size(); g += kGroup) {
+    const std::vector<TopkJob> part(jobs.begin() + g, jobs.begin() + std::min(jobs.size(), g + kGroup));
+    const int rc = topk_many(c, mode, part);
+    if (rc) return rc;
+  }
   return CMM_OK;
 }
 

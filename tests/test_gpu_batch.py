@@ -131,6 +131,45 @@ def test_batch_equals_standalone_and_oracle(cmm, ctx, mix):
     bt.free()
 
 
+def _upper_domain(n1, n3):
+    return sum(max(0, n3 - i - 1) for i in range(n1))
+
+
+@pytest.mark.parametrize("mode", ["all", "upper", "column"])
+def test_batch_topk_equals_per_product(cmm, ctx, mix, mode):
+    """cmm_batch_topk shares the host waits of all products; its results are
+    those of cmm_topk on every product (the same kernels and thresholds),
+    with a different K per product, over products that take the sampled
+    fast path (n1 >= 1024) and ones that take the digit passes."""
+    _say(f"case: batch top-K ({mode}) vs per-product top-K")
+    bt = cmm.Batch(ctx, _problems(cmm, mix))
+    bt.run()
+    Ks = []
+    for q, x in enumerate(mix):
+        if mode == "column":
+            Ks.append(min(1 + q, x["n1"]))
+        else:
+            dom = x["n1"] * x["n3"] if mode == "all" else _upper_domain(x["n1"], x["n3"])
+            Ks.append(min(5 + 7 * q, dom))
+    got = bt.topk(Ks, mode)
+    assert len(got) == len(mix)
+    for q in range(len(mix)):
+        want = bt.sketch(q).topk(Ks[q], mode)
+        for a, b in zip(got[q], want):
+            assert np.array_equal(a, b), (q, mode)
+    # invalid K for one product: nothing is returned, the error names it
+    bad = list(Ks)
+    bad[3] = 0
+    with pytest.raises(cmm.CmmError) as e:
+        bt.topk(bad, mode)
+    assert e.value.code == cmm.CMM_EINVAL
+    bad[3] = mix[3]["n1"] * mix[3]["n3"] + 1
+    with pytest.raises(cmm.CmmError) as e:
+        bt.topk(bad, mode)
+    assert e.value.code == cmm.CMM_EINVAL
+    bt.free()
+
+
 def test_graph_replays_with_eager_work_between(cmm, ctx, mix):
     _say("case: repeated graph replays with operand rescaling between them")
     import torch
