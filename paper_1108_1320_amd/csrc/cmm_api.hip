@@ -86,6 +86,16 @@ void destroy_overlap(cmm::Overlap& ov) {
   ov = cmm::Overlap();
 }
 
+// The second stream for a spectral step on stream `s`: the context's, for
+// work on the context stream that is not being captured into a graph (the
+// pair kernel then runs on `s` itself, before the row kernel).
+const cmm::Overlap* overlap_for(cmm_ctx* c, hipStream_t s) {
+  if (s != c->stream) return nullptr;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+  return st == hipStreamCaptureStatusNone ? &c->ov : nullptr;
+}
+
 int fail(cmm_ctx* c, int code, const std::string& msg) {
   if (c) c->last_error = msg;
   return code;
@@ -487,7 +497,7 @@ int enqueue_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::G
   {
     Scope sc_(c, "fft_mac");
     CMM_HIP(c, cmm::launch_fft_mac(g, side[0], side[1], tw32, (float2*)ptr.p[W_PPART], s,
-                                   s == c->stream ? &c->ov : nullptr));
+                                   overlap_for(c, s)));
   }
   {
     Scope sc_(c, "ifft");
@@ -1849,7 +1859,7 @@ int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B
         side[q].scale = mask;
         CMM_HIP(ctx, cmm::launch_countsketch(dtype, g, side[q], s));
         CMM_HIP(ctx, cmm::launch_fft_mac(g, side[0], side[1], tw32, (float2*)ptr.p[W_PPART], s,
-                                         s == ctx->stream ? &ctx->ov : nullptr));
+                                         overlap_for(ctx, s)));
         CMM_HIP(ctx, cmm::launch_ifft(g, (float2*)ptr.p[W_PPART], (double2*)ptr.p[W_WORK0],
                                       (double2*)ptr.p[W_WORK1], tw64, ctmp, s));
         if (diagm) {
