@@ -147,7 +147,10 @@ __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, 
           v[q] = x;
           amax = fmaxf(amax, fabsf(x));
         }
-        *(float4*)&out[p] = make_float4(v[0], v[1], v[2], v[3]);
+        // streaming store: the sketches are several times larger than the
+        // caches and are read back only by the spectral kernel
+        typedef float v4f __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(v4f{v[0], v[1], v[2], v[3]}, reinterpret_cast<v4f*>(&out[p]));
       }
       for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
       if ((tid & 63) == 0) atomicMax(&smax[par][t], __float_as_uint(amax));   // d <= 63
