@@ -170,6 +170,31 @@ def test_batch_topk_equals_per_product(cmm, ctx, mix, mode):
     bt.free()
 
 
+def test_batch_topk_across_groups(cmm, ctx):
+    """A batch of more than 256 products: the batch top-K runs in groups of
+    256 and writes each product's results at its own offset."""
+    import torch
+    _say("case: batch top-K over 260 small products (two groups)")
+    g = np.random.default_rng(4242)
+    ops, probs, Ks = [], [], []
+    for q in range(260):
+        n1, n3, m = int(g.integers(20, 70)), int(g.integers(20, 70)), int(g.integers(5, 30))
+        At = torch.from_numpy(g.standard_normal((m, n1)).astype(np.float32)).cuda()
+        B = torch.from_numpy(g.standard_normal((m, n3)).astype(np.float32)).cuda()
+        ops.append((At, B))
+        probs.append(cmm.problem(At, B, 256, 1 + q % 3, seed=q))
+        Ks.append(1 + q % 5)
+    bt = cmm.Batch(ctx, probs, keep=ops)
+    bt.run()
+    got = bt.topk(Ks, "all")
+    for q in (0, 1, 255, 256, 257, 259):
+        want = bt.sketch(q).topk(Ks[q], "all")
+        for a, b in zip(got[q], want):
+            assert np.array_equal(a, b), q
+    assert [len(x[0]) for x in got] == Ks
+    bt.free()
+
+
 def test_graph_replays_with_eager_work_between(cmm, ctx, mix):
     _say("case: repeated graph replays with operand rescaling between them")
     import torch
