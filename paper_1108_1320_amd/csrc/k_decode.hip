@@ -268,9 +268,14 @@ __global__ __launch_bounds__(1024) void k_topk_final(const TopkCand* __restrict_
 // smaller i) strictly below the previous pick.  STORE keeps the column's
 // keys in LDS (n1 <= kMaxColumnKeys); otherwise every round decodes the
 // column again.
+constexpr int kColList = 256;   // survivors listed by the per-column sampled path
+// dynamic LDS of the stored per-column kernel: the keys, then (when it fits)
+// the survivor list
+constexpr size_t kColumnLds = (size_t)kMaxColumnKeys * 4;
+
 template <int D, bool STORE>
 __global__ __launch_bounds__(256) void k_topk_column(DecodeDesc dd, int K, int64_t* __restrict__ oi,
-                                                     float* __restrict__ ov) {
+                                                     float* __restrict__ ov, bool list) {
   extern __shared__ uint32_t keys[];
   __shared__ unsigned long long wbest[4];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -315,23 +320,46 @@ __global__ __launch_bounds__(256) void k_topk_column(DecodeDesc dd, int K, int64
         unsigned long long lastp = ~0ull;
         for (int r = 0; r < rr; ++r) lastp = best_below(ns, lastp);
         const uint32_t T = (uint32_t)(lastp >> 32);
+        // rows reaching T, with their estimates, in arrival order (in the
+        // dynamic LDS after the keys when the launch made room: list = true)
         __shared__ int survivors;
+        uint32_t* skey = keys + dd.n1;
+        int* srow = reinterpret_cast<int*>(skey + kColList);
+        float* sval = reinterpret_cast<float*>(srow + kColList);
+        const int cap = list ? kColList : 0;
         if (tid == 0) survivors = 0;
         __syncthreads();
-        int mine = 0;
         for (int i = tid; i < dd.n1; i += 256) {
           HashVec<D> h1;
           load_hash<D>(h1, dd.hs1, dd.n1, i, dd.d);
           const float e = estimate_above<D>(dd, h1.v, h2.v, __uint_as_float(T));
           const bool keep = e == e && __float_as_uint(fabsf(e)) >= T;
           keys[i] = keep ? __float_as_uint(fabsf(e)) : 0u;
-          mine += keep;
+          if (keep) {
+            const int slot = atomicAdd(&survivors, 1);
+            if (slot < cap) { skey[slot] = __float_as_uint(fabsf(e)); srow[slot] = i; sval[slot] = e; }
+          }
         }
-        atomicAdd(&survivors, mine);
         __syncthreads();
+        const int S = survivors;
         // exact when at least K rows reach T: every row left at key 0 lies
         // below all of them
-        exact = survivors < K;
+        exact = S < K;
+        if (!exact && S <= cap) {
+          // the K largest survivors by (key desc, row asc): each survivor's
+          // rank is the number of survivors ahead of it
+          for (int a = tid; a < S; a += 256) {
+            const uint32_t ka = skey[a];
+            const int ia = srow[a];
+            int rank = 0;
+            for (int c = 0; c < S; ++c) rank += (skey[c] > ka) || (skey[c] == ka && srow[c] < ia);
+            if (rank < K) {
+              oi[(int64_t)j * K + rank] = ia;
+              ov[(int64_t)j * K + rank] = sval[a];
+            }
+          }
+          return;
+        }
       }
     }
     if (exact) {
@@ -440,10 +468,14 @@ hipError_t launch_topk_final(const TopkCand* cand, const uint32_t* count, int ca
 
 hipError_t launch_topk_column(const DecodeDesc& dd, int K, int64_t* oi, float* ov, hipStream_t s) {
   const bool store = dd.n1 <= kMaxColumnKeys;
-  const size_t lds = store ? (size_t)dd.n1 * sizeof(uint32_t) : 0;
+  // the survivor list follows the keys when both fit in the 160 KB
+  const size_t keys = (size_t)dd.n1 * sizeof(uint32_t);
+  const size_t list_bytes = (size_t)kColList * (sizeof(uint32_t) + sizeof(int) + sizeof(float));
+  const bool list = store && keys + list_bytes <= kColumnLds;
+  const size_t lds = store ? keys + (list ? list_bytes : 0) : 0;
 #define CMM_K(DV)                                                                              \
-  if (store) hipLaunchKernelGGL((k_topk_column<DV, true>), dim3(dd.n3), dim3(256), lds, s, dd, K, oi, ov); \
-  else hipLaunchKernelGGL((k_topk_column<DV, false>), dim3(dd.n3), dim3(256), 0, s, dd, K, oi, ov)
+  if (store) hipLaunchKernelGGL((k_topk_column<DV, true>), dim3(dd.n3), dim3(256), lds, s, dd, K, oi, ov, list); \
+  else hipLaunchKernelGGL((k_topk_column<DV, false>), dim3(dd.n3), dim3(256), 0, s, dd, K, oi, ov, false)
   CMM_DISPATCH_D(dd.d, CMM_K)
 #undef CMM_K
   return hipGetLastError();
@@ -454,7 +486,7 @@ hipError_t launch_topk_column(const DecodeDesc& dd, int K, int64_t* oi, float* o
 hipError_t prepare_decode() {
 #define CMM_P(DV)                                                                          \
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_topk_column<DV, true>),          \
-                          hipFuncAttributeMaxDynamicSharedMemorySize, kMaxColumnKeys * 4);  \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kColumnLds);     \
   if (e != hipSuccess) return e;
   hipError_t e = hipSuccess;
   CMM_P(0) CMM_P(1) CMM_P(2) CMM_P(3) CMM_P(4) CMM_P(5) CMM_P(6) CMM_P(7) CMM_P(8)
