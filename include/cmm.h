@@ -34,7 +34,13 @@
  *   per repetition and per function h1, s1, h2, s2 (in that order).  With a
  *   seed the pairs come from the SplitMix64 stream of the seed: outputs
  *   z_{8t+2f+1}, z_{8t+2f+2} give a = 1 + z mod (2^61-2), c = z' mod (2^61-1).
- * - b must be a power of two in [16, 2^20]; 1 <= d <= 63.
+ * - b must be a power of two in [16, 2^20]; 1 <= d <= 63.  The transform
+ *   splits b = R * C with C <= 2^13 (two C-point buffers in LDS) and
+ *   R <= 256 (its row-weight table and 16-bit row field), which caps the
+ *   design at 2^21; 2^20 is the largest length the test suite runs.
+ * - fp8 scales are per hashed index (scaleA[n1], scaleB[n3]): one float per
+ *   column of each stored k-major array, multiplied into every value of
+ *   that index before it is hashed.
  * - Objects are library-owned: free sketches with cmm_sketch_free() before
  *   destroying their context with cmm_ctx_destroy().
  * - A context and its sketches are used by one host thread at a time (the

@@ -168,7 +168,9 @@ __device__ __forceinline__ void fetch(Batch<kU>& bt, const float* sa, const uint
 // are an order of magnitude slower, and integer sums do not depend on the
 // order of the adds).  A slot gathers at most R buckets and |w| = 1, so with
 // the column's max |value| cmax the slot sums stay below R cmax; values are
-// scaled by 2^(30 - e) with R cmax < 2^e and rounded to int32.  The real and
+// scaled by 2^(30 - e) with R cmax < 2^e and converted to int32 by
+// truncation toward zero, so each folded value loses less than one unit
+// 2^(e - 30) <= 2 R cmax 2^-30 (frexp puts 2^e in (R cmax, 2 R cmax]).  The real and
 // imaginary parts travel packed in one 64-bit add, im * 2^32 + re: the sum
 // is exact modulo 2^64 and both 32-bit sums are recovered from it because
 // each stays inside int32.

@@ -1,6 +1,6 @@
-// Inverse transform of the accumulated spectrum (Figure 1: p[t] :=
-// FFT^-1(p[t])), the diagonal correction of Section 3.2, and small linear
-// helpers.  Everything here is float64.
+// Inverse transform of the accumulated spectrum (Figure 1: c_t is the
+// inverse DFT of the summed spectrum P_t), the diagonal correction of
+// Section 3.2, and small linear helpers.  Everything here is float64.
 //
 // The FFT kernel leaves, per k-split, rows f1 in [0, R/2] of the spectrum
 // (frequency f = f1 + R f2).  The reduction sums the k-splits in a fixed

@@ -37,6 +37,42 @@ def test_hash_params_ranges():
     assert len({int(x) for x in pr.ravel()}) == 8 * 7
 
 
+def test_hash_params_seed0_known_answers():
+    """Repetition 0's h1 and s1 parameters for seed 0 equal the values worked
+    out by hand from the published SplitMix64 outputs z1..z4 of seed 0
+    (tests/golden/hash_params_seed0.txt): catches an off-by-one in the output
+    index, swapped a/c, or a wrong modulus."""
+    with open(os.path.join(GOLDEN, "hash_params_seed0.txt")) as f:
+        rows = {r[0]: (int(r[1]), int(r[2])) for r in
+                (l.split() for l in f if l.strip() and not l.startswith("#"))}
+    pr = O.hash_params(0, 1)
+    assert (int(pr[0, 0, 0]), int(pr[0, 0, 1])) == rows["h1"]
+    assert (int(pr[0, 1, 0]), int(pr[0, 1, 1])) == rows["s1"]
+    # the hash values those parameters give, worked out by hand: g(0) = c,
+    # g(1) = a + c (below p here), h = g mod 1024, s from the parity of g
+    a, c = rows["h1"]
+    h1, s1, _, _ = O.hash_tables(pr, 2, 1, 1024)
+    assert h1[0].tolist() == [c % 1024, (a + c) % 1024] == [503, 949]
+    a, c = rows["s1"]
+    assert s1[0].tolist() == [1 - 2 * (c % 2), 1 - 2 * ((a + c) % 2)] == [-1, -1]
+
+
+def test_hash_params_counter_layout():
+    """SplitMix64 is a counter generator: output k of seed s is output 1 of
+    seed s + (k - 1) * gamma (mod 2^64).  Function f of repetition t reads
+    outputs 8t + 2f + 1 and 8t + 2f + 2, so its parameters must equal the
+    repetition-0 h1 parameters of the seed advanced by (8t + 2f) gamma; with
+    the known answers above this pins every (t, f) slot."""
+    gamma = 0x9E3779B97F4A7C15
+    for seed in (0, 2002, 2**64 - 5):
+        pr = O.hash_params(seed, 4)
+        for t in range(4):
+            for f in range(4):
+                moved = (seed + (8 * t + 2 * f) * gamma) % 2**64
+                q = O.hash_params(moved, 1)
+                assert (int(pr[t, f, 0]), int(pr[t, f, 1])) == (int(q[0, 0, 0]), int(q[0, 0, 1])), (seed, t, f)
+
+
 def _mersenne_mod(v: int) -> int:
     """v mod (2^61-1) by repeated folding of 61-bit digits (an independent
     route to the same residue)."""
@@ -241,6 +277,36 @@ def test_topk_order_and_ties():
     sel_lin, sel_val = O.topk(vals, lin, 4)
     assert sel_lin.tolist() == [2, 4, 7, 3]
     assert sel_val.tolist() == [-3.0, -3.0, 3.0, 2.0]
+
+
+def test_candidates_hand_listing():
+    """The candidate domains written out by hand: every (i, j) of a 2 x 3
+    product in linear-index order, and the n(n-1)/2 pairs i < j of n = 4."""
+    i, j = O.candidates("all", 2, 3)
+    assert list(zip(i.tolist(), j.tolist())) == [(0, 0), (0, 1), (0, 2), (1, 0), (1, 1), (1, 2)]
+    i, j = O.candidates("upper", 4, 4)
+    assert list(zip(i.tolist(), j.tolist())) == [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]
+    for n in (1, 2, 5, 37):
+        i, j = O.candidates("upper", n, n)
+        assert len(i) == n * (n - 1) // 2
+        assert np.all(i < j) and len(set(zip(i.tolist(), j.tolist()))) == len(i)
+    assert len(O.candidates("all", 7, 3)[0]) == 21
+
+
+def test_topk_per_column_hand_example_with_ties():
+    """Per-column selection on a hand example: column 0 has a tie of |3| at
+    rows 1 and 2 (smaller row first), column 1 a three-way tie of |2| at
+    rows 0, 1 and 3 of which only the two smallest rows are kept."""
+    C = np.array([[1.0, -2.0],
+                  [-3.0, 2.0],
+                  [3.0, 0.5],
+                  [0.0, -2.0]])
+    rows, vals = O.topk_per_column(C, 2)
+    assert rows.tolist() == [[1, 2], [0, 1]]
+    assert vals.tolist() == [[-3.0, 3.0], [-2.0, 2.0]]
+    rows, vals = O.topk_per_column(C, 4)
+    assert rows.tolist() == [[1, 2, 0, 3], [0, 1, 3, 2]]
+    assert vals.tolist() == [[-3.0, 3.0, 1.0, 0.0], [-2.0, 2.0, -2.0, 0.5]]
 
 
 def test_theorem2_unbiased_and_variance():
