@@ -143,6 +143,28 @@ const char* cmm_last_error(const cmm_ctx* ctx);
 int cmm_ctx_profile(cmm_ctx* ctx, int enable);
 int cmm_ctx_profile_read(cmm_ctx* ctx, const char* name, double* total_ms, int64_t* launches);
 
+/* Bytes the named kernels move to and from device memory by design, summed
+ * over the launches timed since profiling was enabled.  Only "countsketch"
+ * is recorded: the stored operands (and fp8 scales) read once, and the
+ * count-sketch positions written (the layout's padded segments, W * lseg
+ * per side, repetition and k) plus one column maximum per side, repetition
+ * and k.  Recorded for synchronous dense products (not for CMM_ASYNC,
+ * sparse operands or batches); the segment lengths are read back after the
+ * product, outside its kernels.  Unknown names read 0. */
+int cmm_ctx_profile_bytes(cmm_ctx* ctx, const char* name, double* read_bytes, double* written_bytes);
+
+/* HBM stream measurement, for comparing a kernel with what plain streams of
+ * the same shape reach on this device: `reps` timed launches (after one
+ * untimed) of a kernel that reads read_bytes (16-byte loads) and writes
+ * write_bytes (16-byte stores, streaming non-temporal ones when
+ * `nontemporal`), in r = write_bytes / read_bytes contiguous output planes
+ * per input element when both are non-zero.  Sizes are multiples of 16 and
+ * write_bytes a multiple of read_bytes when both are set (CMM_EINVAL
+ * otherwise).  Allocates and frees its buffers.  *ms_per_launch receives
+ * the HIP-event time per launch on the context stream. */
+int cmm_stream_probe(cmm_ctx* ctx, int64_t read_bytes, int64_t write_bytes, int32_t nontemporal,
+                     int32_t reps, double* ms_per_launch);
+
 /* ---- the sketch (COMPRESSEDPRODUCT, Figure 1) ------------------------- */
 
 /* Square float32 form: A (n x n, column-major, lda = n), B (n x n,

@@ -53,6 +53,8 @@ _SIGS = {
     "cmm_last_error": (C.c_char_p, [_P]),
     "cmm_ctx_profile": (C.c_int, [_P, C.c_int]),
     "cmm_ctx_profile_read": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(_I64)]),
+    "cmm_ctx_profile_bytes": (C.c_int, [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "cmm_stream_probe": (C.c_int, [_P, _I64, _I64, _I32, _I32, C.POINTER(C.c_double)]),
     "cmm_sketch_product": (C.c_int, [_P, _P, _P, _I64, _I64, _I32, _U64, C.POINTER(_P)]),
     "cmm_sketch_product_ex": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P,
                                         _I64, _I32, _U64, _P, _U32, C.POINTER(_P)]),
@@ -166,6 +168,20 @@ def cmm_ctx_profile_read(ctx, name: str):
     _check(load().cmm_ctx_profile_read(ctx, name.encode(), C.byref(ms), C.byref(n)),
            "cmm_ctx_profile_read", ctx)
     return ms.value, n.value
+
+
+def cmm_ctx_profile_bytes(ctx, name: str):
+    rd = C.c_double(); wr = C.c_double()
+    _check(load().cmm_ctx_profile_bytes(ctx, name.encode(), C.byref(rd), C.byref(wr)),
+           "cmm_ctx_profile_bytes", ctx)
+    return rd.value, wr.value
+
+
+def cmm_stream_probe(ctx, read_bytes: int, write_bytes: int, nontemporal: bool, reps: int):
+    ms = C.c_double()
+    _check(load().cmm_stream_probe(ctx, int(read_bytes), int(write_bytes), int(nontemporal), int(reps),
+                                   C.byref(ms)), "cmm_stream_probe", ctx)
+    return ms.value
 
 
 def cmm_sketch_product(ctx, A, B, n: int, b: int, d: int, seed: int):
@@ -411,6 +427,14 @@ class Context:
 
     def profile_read(self, name: str):
         return cmm_ctx_profile_read(self.handle, name)
+
+    def profile_bytes(self, name: str):
+        """(read, written) bytes the named kernels moved by design while profiling."""
+        return cmm_ctx_profile_bytes(self.handle, name)
+
+    def stream_probe(self, read_bytes: int, write_bytes: int, nontemporal: bool = False, reps: int = 10):
+        """HIP-event ms per launch of a plain HBM stream of this shape."""
+        return cmm_stream_probe(self.handle, read_bytes, write_bytes, nontemporal, reps)
 
     def autotune(self, n1, m, n3, b, d, dtype="f32"):
         """Tune the size class of these sizes; returns ((log2c, kmax, cs_blocks), ms)."""

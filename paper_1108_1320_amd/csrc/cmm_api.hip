@@ -52,6 +52,8 @@ struct cmm_ctx {
   bool prof = false;
   std::vector<Pending> pending;
   std::map<std::string, std::pair<double, int64_t>> prof_acc;
+  std::vector<hipEvent_t> event_pool;   // timing events reused across scopes
+  std::map<std::string, std::pair<double, double>> prof_bytes;   // read, written
   uint32_t* pinned_u32 = nullptr;   // small pinned host scratch
   char* pinned = nullptr;           // pinned staging of downloads (pinned_cap bytes)
   size_t pinned_cap = 0;
@@ -157,14 +159,33 @@ void dfree(cmm_ctx* c, void* p) {
   c->free_blocks.emplace(it->second, p);
 }
 
+// A timing event from the context's pool (created on first use).
+hipEvent_t take_event(cmm_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+  return e;
+}
+
 struct Scope {
   cmm_ctx* c;
   const char* name;
   hipEvent_t a = nullptr, b = nullptr;
   Scope(cmm_ctx* cc, const char* nm) : c(cc), name(nm) {
-    if (c->prof && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+    if (!c->prof) return;
+    a = take_event(c);
+    b = take_event(c);
+    if (a && b) {
       hipEventRecord(a, c->stream);
-    else { a = b = nullptr; }
+    } else {
+      if (a) c->event_pool.push_back(a);
+      if (b) c->event_pool.push_back(b);
+      a = b = nullptr;
+    }
   }
   ~Scope() {
     if (a && b) {
@@ -183,8 +204,8 @@ void drain_profile(cmm_ctx* c) {
       acc.first += ms;
       acc.second += 1;
     }
-    hipEventDestroy(p.a);
-    hipEventDestroy(p.b);
+    c->event_pool.push_back(p.a);
+    c->event_pool.push_back(p.b);
   }
   c->pending.clear();
 }
@@ -554,6 +575,30 @@ Operands slab_operands(const Operands& op, int64_t k0) {
   return o;
 }
 
+// Bytes the count-sketch launches of a finished dense product moved by
+// design, added to the "countsketch" byte record of the context: the stored
+// operands (and fp8 scales) read once, and, per side, repetition and k, the
+// W * lseg positions of the layout written (padding included) plus one
+// column maximum.  Needs the layout's segment lengths from the device.
+int account_countsketch(cmm_ctx* c, const cmm_sketch* sk, const Operands& op,
+                        const cmm::Geometry& g, const WsPtrs& ptr, hipStream_t s) {
+  std::vector<int32_t> l0((size_t)sk->d), l1((size_t)sk->d);
+  const size_t nb = sizeof(int32_t) * sk->d;
+  int rc = download(c, s, {{l0.data(), ptr.p[W_LSEG0], nb}, {l1.data(), ptr.p[W_LSEG1], nb}});
+  if (rc) return rc;
+  const double esz = op.dtype == CMM_F32 ? 4.0 : (op.dtype == CMM_BF16 ? 2.0 : 1.0);
+  double rd = esz * (double)sk->m * (double)(sk->n1 + sk->n3);
+  if (op.scaleA) rd += 4.0 * (double)sk->n1;
+  if (op.scaleB) rd += 4.0 * (double)sk->n3;
+  double wr = 0.0;
+  for (int t = 0; t < sk->d; ++t) wr += 4.0 * (double)sk->m * g.W * (double)(l0[t] + l1[t]);
+  wr += 4.0 * 2.0 * (double)sk->d * (double)sk->m;
+  auto& acc = c->prof_bytes["countsketch"];
+  acc.first += rd;
+  acc.second += wr;
+  return CMM_OK;
+}
+
 // One product on the context stream with a workspace from the cache.
 // A product whose workspace would exceed the context's limit runs as
 // consecutive k-slabs: the sketch of AB is the sum of the sketches of the
@@ -608,6 +653,8 @@ int run_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Tunin
     if (e1 != hipSuccess || e2 != hipSuccess) rc = fail(c, CMM_EHIP, "stream synchronisation failed");
     else *overflowed = c->pinned_u32[0] != 0;
   }
+  if (rc == CMM_OK && !async && c->prof && op.dtype != cmm::kSparseF32)
+    rc = account_countsketch(c, sk, op, g, ptr, s);
   ws_release(c, owned);   // stream-ordered reuse: later work on this stream follows
   return rc;
 }
@@ -1339,6 +1386,7 @@ int cmm_ctx_destroy(cmm_ctx* ctx) {
   hipStreamSynchronize(ctx->stream);
   destroy_overlap(ctx->ov);
   for (auto& p : ctx->pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+  for (hipEvent_t e : ctx->event_pool) hipEventDestroy(e);
   for (auto& kv : ctx->sizes) hipFree(kv.first);
   for (auto& kv : ctx->twiddles) { hipFree(kv.second.first); hipFree(kv.second.second); }
   if (ctx->pinned_u32) hipHostFree(ctx->pinned_u32);
@@ -1353,6 +1401,15 @@ int cmm_ctx_profile(cmm_ctx* ctx, int enable) {
   drain_profile(ctx);
   ctx->prof = enable != 0;
   ctx->prof_acc.clear();
+  ctx->prof_bytes.clear();
+  return CMM_OK;
+}
+
+int cmm_ctx_profile_bytes(cmm_ctx* ctx, const char* name, double* read_bytes, double* written_bytes) {
+  if (!valid_ctx(ctx) || !name) return CMM_EINVAL;
+  auto it = ctx->prof_bytes.find(name);
+  if (read_bytes) *read_bytes = it == ctx->prof_bytes.end() ? 0.0 : it->second.first;
+  if (written_bytes) *written_bytes = it == ctx->prof_bytes.end() ? 0.0 : it->second.second;
   return CMM_OK;
 }
 
@@ -1363,6 +1420,51 @@ int cmm_ctx_profile_read(cmm_ctx* ctx, const char* name, double* total_ms, int64
   if (total_ms) *total_ms = it == ctx->prof_acc.end() ? 0.0 : it->second.first;
   if (launches) *launches = it == ctx->prof_acc.end() ? 0 : it->second.second;
   return CMM_OK;
+}
+
+int cmm_stream_probe(cmm_ctx* ctx, int64_t read_bytes, int64_t write_bytes, int32_t nontemporal,
+                     int32_t reps, double* ms_per_launch) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  if (read_bytes < 0 || write_bytes < 0 || (read_bytes == 0 && write_bytes == 0) ||
+      read_bytes % 16 || write_bytes % 16 || reps < 1 || !ms_per_launch ||
+      (read_bytes > 0 && write_bytes > 0 && write_bytes % read_bytes))
+    return fail(ctx, CMM_EINVAL, "stream probe: sizes must be multiples of 16, write a multiple of read");
+  CMM_HIP(ctx, hipSetDevice(ctx->device));
+  void* src = nullptr;
+  void* dst = nullptr;
+  float* sink = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = CMM_OK;
+  if ((read_bytes && hipMalloc(&src, (size_t)read_bytes) != hipSuccess) ||
+      (write_bytes && hipMalloc(&dst, (size_t)write_bytes) != hipSuccess) ||
+      hipMalloc((void**)&sink, 4096 * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    rc = fail(ctx, CMM_ENOMEM, "stream probe buffers");
+  }
+  if (rc == CMM_OK && src && hipMemsetAsync(src, 0, (size_t)read_bytes, ctx->stream) != hipSuccess)
+    rc = fail(ctx, CMM_EHIP, "stream probe fill");
+  if (rc == CMM_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+    rc = fail(ctx, CMM_EHIP, "stream probe events");
+  const bool nt = nontemporal != 0;
+  // one untimed launch, then `reps` timed ones
+  if (rc == CMM_OK && cmm::launch_stream_probe(src, dst, sink, read_bytes, write_bytes, nt, ctx->stream) != hipSuccess)
+    rc = fail(ctx, CMM_EHIP, "stream probe launch");
+  if (rc == CMM_OK && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = fail(ctx, CMM_EHIP, "event");
+  for (int r = 0; rc == CMM_OK && r < reps; ++r)
+    if (cmm::launch_stream_probe(src, dst, sink, read_bytes, write_bytes, nt, ctx->stream) != hipSuccess)
+      rc = fail(ctx, CMM_EHIP, "stream probe launch");
+  if (rc == CMM_OK && hipEventRecord(e1, ctx->stream) != hipSuccess) rc = fail(ctx, CMM_EHIP, "event");
+  float ms = 0.0f;
+  if (rc == CMM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    rc = fail(ctx, CMM_EHIP, "stream probe timing");
+  if (rc == CMM_OK) *ms_per_launch = ms / reps;
+  hipStreamSynchronize(ctx->stream);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (src) hipFree(src);
+  if (dst) hipFree(dst);
+  if (sink) hipFree(sink);
+  return rc;
 }
 
 int cmm_sketch_product(cmm_ctx* ctx, const float* A, const float* B, int64_t n, int64_t b,

@@ -212,6 +212,8 @@ hipError_t launch_nnz_weights(uint64_t seed, uint64_t offset, int n, const float
 hipError_t launch_nnz_zeros(const double* c, int d, int64_t b, double rel, int64_t* zeros,
                             hipStream_t s);
 hipError_t launch_fill_random(void* X, int64_t count, int dtype, uint64_t seed, hipStream_t s);
+hipError_t launch_stream_probe(const void* src, void* dst, float* sink, int64_t read_bytes,
+                               int64_t write_bytes, bool nt, hipStream_t s);
 
 struct DecodeDesc {
   const int32_t* hs1;   // [d][n1]

@@ -132,20 +132,50 @@ def e4m3fn_grid() -> np.ndarray:
 
 
 _E4M3 = e4m3fn_grid()
+# float32 value of every code 0..255 (sign bit 0x80; the two NaN codes 0x7F
+# and 0xFF, which the encoder never produces, read as NaN)
+_E4M3_SIGNED32 = np.array([(-1.0 if c & 0x80 else 1.0) * _E4M3[c & 0x7F] if c & 0x7F != 0x7F else np.nan
+                           for c in range(256)], dtype=np.float32)
+
+
+def _e4m3fn_chunk(v: np.ndarray) -> np.ndarray:
+    """e4m3fn codes of a float64 chunk from its IEEE bits: for |v| >= 2^-6 the
+    top 3 of the 52 mantissa bits are rounded half-to-even (a carry moves to
+    the next binade); below 2^-6 the value is rounded to a multiple of 2^-9
+    (subnormal codes 0..7, 8 being the smallest normal).  Saturates at 448."""
+    a = np.minimum(np.abs(v), 448.0)
+    bits = a.view(np.uint64)
+    e = (bits >> np.uint64(52)).astype(np.int64) - 1023
+    mant = bits & np.uint64((1 << 52) - 1)
+    q = (mant >> np.uint64(49)).astype(np.int64)
+    rem = mant & np.uint64((1 << 49) - 1)
+    half = np.uint64(1 << 48)
+    q += ((rem > half) | ((rem == half) & (q % 2 == 1))).astype(np.int64)
+    carry = q == 8
+    normal = ((e + 7 + carry) << 3) | np.where(carry, 0, q)
+    code = np.where(a < 2.0 ** -6, np.rint(a * 512.0).astype(np.int64), normal)
+    return (code | np.where(np.signbit(v), 0x80, 0)).astype(np.uint8)
 
 
 def e4m3fn_encode(x) -> np.ndarray:
-    """float -> OCP e4m3fn bits (uint8), round to nearest even, saturating."""
+    """float -> OCP e4m3fn bits (uint8), round to nearest even, saturating;
+    chunks of 2^21 values on a few threads."""
+    from concurrent.futures import ThreadPoolExecutor
     x = np.asarray(x, dtype=np.float64)
-    a = np.minimum(np.abs(x), _E4M3[-1])
-    hi = np.clip(np.searchsorted(_E4M3, a, side="left"), 0, 126)
-    lo = np.clip(hi - 1, 0, 126)
-    dlo = np.abs(a - _E4M3[lo])
-    dhi = np.abs(_E4M3[hi] - a)
-    pick_hi = (dhi < dlo) | ((dhi == dlo) & (hi % 2 == 0))
-    code = np.where(pick_hi, hi, lo).astype(np.uint8)
-    code = np.where(np.signbit(x), code | np.uint8(0x80), code).astype(np.uint8)
-    return code
+    out = np.empty(x.shape, dtype=np.uint8)
+    xf, of = x.reshape(-1), out.reshape(-1)
+    step = 1 << 21
+
+    def one(s0):
+        of[s0:s0 + step] = _e4m3fn_chunk(xf[s0:s0 + step])
+    starts = range(0, xf.size, step)
+    if xf.size <= step:
+        for s0 in starts:
+            one(s0)
+    else:
+        with ThreadPoolExecutor(max_workers=8) as ex:
+            list(ex.map(one, starts))
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -232,8 +262,7 @@ def _decode_store(store, dtype, scale):
         return store, None, store.astype(np.float64)
     if dtype == "bf16":
         return store, None, (store.astype(np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
-    mag = _E4M3[(store & 0x7F).astype(np.int64)]
-    val = np.where((store & 0x80) != 0, -mag, mag).astype(np.float32) * scale.astype(np.float32)[None, :]
+    val = _E4M3_SIGNED32[store] * scale.astype(np.float32)[None, :]
     return store, scale, val.astype(np.float64)
 
 
