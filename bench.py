@@ -19,6 +19,14 @@ overlap and planted recall against the headline run, and, with the oracle,
 each format's arithmetic error (against the float64 oracle of the values it
 multiplies) apart from its quantisation error.
 
+The default run also measures the other single-product workloads
+(``configs``: covariance 256 f32, DCT 8192 bf16 with top-16 per column,
+covariance 16384 fp8 with top-256), each with its own tuning, step time,
+per-kernel times, spectral roofline and count-sketch HBM rate, and compares
+the count sketch with plain HBM streams of its shape (``stream_ceiling``).
+Step times come from a region with the library's timing events off; a second
+region of the same steps with the events on gives the per-kernel times.
+
 The batched form (``batched_form``; ``--workload 5`` makes it the headline):
 64 covariance products, n = m log-uniform in [512, 8192], b = next power of
 two of 8n, d = 5, bf16 operands, diagonal subtracted, recorded once into one
@@ -74,6 +82,12 @@ def parse():
                    help="use the built-in geometry instead of tuning the size class first")
     p.add_argument("--geometry", type=str, default=None,
                    help="log2c,kmax,cs_blocks: run the headline with this geometry instead of tuning")
+    p.add_argument("--no-configs", action="store_true",
+                   help="skip the per-workload measurements of the other benchmark workloads")
+    p.add_argument("--no-stream", action="store_true", help="skip the HBM stream-ceiling probes")
+    p.add_argument("--stream-ceiling", action="store_true",
+                   help="only measure plain HBM streams (read, write, copy, 1:5 read:write; ordinary "
+                        "and streaming stores) and print them")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -95,8 +109,10 @@ def copy_calibration():
 
 
 def run_timed(ctx, w, steps, warmup):
-    """Time ``steps`` whole steps (after ``warmup``) of workload ``w`` with the
-    library's kernel timing events on; returns the last product for checks."""
+    """Time ``steps`` whole steps (after ``warmup``) of workload ``w``.  The
+    timed region runs with the library's timing events off; a second region
+    of the same steps with the events on gives the per-kernel times and the
+    count sketch's byte record.  Returns the last product for checks."""
     import numpy as np
     import torch
     import paper_1108_1320_amd as cmm
@@ -117,19 +133,97 @@ def run_timed(ctx, w, steps, warmup):
         sk, _ = step()
         sk.free()
     torch.cuda.synchronize()
-    ctx.profile(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         sk, res = step()
         sk.free()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        sk, res = step()
+        sk.free()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     kern = {k: ctx.profile_read(k) for k in KERNELS}
+    cs_bytes = ctx.profile_bytes("countsketch")
     ctx.profile(False)
     sk, res = step()     # one more product, kept for the checks
-    return {"ms": (t1 - t0) * 1e3 / steps, "kern": kern, "sketch": sk, "topk": res,
+    return {"ms": (t1 - t0) * 1e3 / steps, "ms_profiled": (t3 - t2) * 1e3 / steps, "kern": kern,
+            "cs_bytes": cs_bytes, "sketch": sk, "topk": res,
             "input_bytes": (w.n1 * w.m + w.m * w.n3) * esz}
+
+
+def describe(w):
+    if w.mode == "upper":
+        return f"{w.name}: covariance n=m={w.n1} b={w.b} d={w.d} top-{w.K} i<j, diagonal subtracted, {w.dtype}"
+    return f"{w.name}: n1={w.n1} m={w.m} n3={w.n3} b={w.b} d={w.d} top-{w.K} {w.mode}, {w.dtype}"
+
+
+def measure(ctx, w, steps, warmup, autotune=True, geometry=None):
+    """One workload: tuning, timed steps, per-kernel times, the spectral
+    kernels' roofline and the count sketch's HBM rate.  Returns
+    (summary dict, run_timed result)."""
+    n1, m, n3, b, d = w.n1, w.m, w.n3, w.b, w.d
+    tuned = None
+    if geometry:
+        ctx.set_tuning(n1, m, n3, b, d, w.dtype, tuple(geometry))
+    elif autotune:
+        t0 = time.perf_counter()
+        tu, tms = ctx.autotune(n1, m, n3, b, d, w.dtype)
+        tuned = {"log2c_kmax_csblocks": list(tu), "product_ms": round(tms, 4),
+                 "seconds": round(time.perf_counter() - t0, 2)}
+    r = run_timed(ctx, w, steps, warmup)
+    ms, kern, input_bytes = r["ms"], r["kern"], r["input_bytes"]
+    value = input_bytes / (ms * 1e-3) / 1e9
+    fft_ms, fft_n = kern["fft_mac"]
+    fft_avg_ms = fft_ms / max(fft_n, 1)
+    flop = nominal_fft_mac_flop(m, b, d)
+    achieved_tflops = flop / (fft_avg_ms * 1e-3) / 1e12
+    cs_ms, cs_n = kern["countsketch"]
+    cs_avg_ms = cs_ms / max(cs_n, 1)
+    cs_rd, cs_wr = r["cs_bytes"]
+    cs_bytes = (cs_rd + cs_wr) / max(cs_n, 1)        # bytes the two launches move, padding included
+    nb = expected_nonempty(n1, b) + expected_nonempty(n3, b)
+    cs_bytes_nb = input_bytes + d * m * nb * 4      # expected non-empty buckets only
+    geom = list(ctx.tuning(n1, m, n3, b, d, w.dtype))
+    out = {
+        "workload": describe(w), "dtype": w.dtype, "n1": n1, "m": m, "n3": n3, "b": b, "d": d,
+        "K": w.K, "topk_mode": w.mode, "input_bytes": input_bytes, "geometry": geom,
+        "autotune": tuned, "steps": steps, "warmup": warmup,
+        "ms_per_step": round(ms, 4), "value": round(value, 3), "unit": "GB/s",
+        "hbm_frac": round(value / HBM_PEAK_GBPS, 5),
+        "input_elements_per_s": round((n1 * m + m * n3) / (ms * 1e-3), 1),
+        "nominal_fft_gflops": round(flop / (ms * 1e-3) / 1e9, 1),
+        "ms_per_step_with_kernel_events": round(r["ms_profiled"], 4),
+        "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in kern.items()},
+        "roofline": {
+            "kernel": "fft_mac",
+            "kernels": ["k_fft_mac", "k_fft_mac_pair"],
+            "bound": "alu",
+            "achieved": round(achieved_tflops, 3),
+            "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+            "traffic": traffic_record(w, geom),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "flop_per_launch": flop,
+            "avg_launch_ms": round(fft_avg_ms, 4),
+        },
+        "countsketch": {
+            "avg_ms": round(cs_avg_ms, 4),
+            "bytes_per_launch_pair": cs_bytes,
+            "achieved": round(cs_bytes / (cs_avg_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(cs_bytes / (cs_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "bytes_read": cs_rd / max(cs_n, 1), "bytes_written": cs_wr / max(cs_n, 1),
+            "bytes_expected_nonempty_only": cs_bytes_nb,
+            "frac_expected_nonempty_only": round(cs_bytes_nb / (cs_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        },
+        "decode_topk_ms": round(kern["decode"][0] / max(kern["decode"][1], 1), 4),
+    }
+    return out, r
 
 
 def run_batched(ctx, steps, warmup, with_oracle=True):
@@ -195,6 +289,7 @@ def run_batched(ctx, steps, warmup, with_oracle=True):
         "create_s": round(create_s, 2), "generate_s": round(gen_s, 2),
         "planted_recall": round(hits / sum(len(w.planted) for w in ws), 4),
     }
+    out["roofline"] = batched_roofline(out, ws)
     if with_oracle:
         from oracle import cmm_oracle as O
         worst = 0.0
@@ -371,6 +466,48 @@ def planted_recall(w, oi, oj):
     return round(len(got & want) / max(len(want), 1), 4)
 
 
+def stream_ceiling(ctx, gib=1.0, reps=10):
+    """What plain HBM streams reach on this GPU, for the count sketch's
+    access pattern: reads only, writes only, a copy, and reads with five
+    times as many bytes written in five output planes (the count sketch
+    writes about 5.3 bytes per byte it reads at covariance 4096), each with
+    ordinary and with streaming (non-temporal) stores."""
+    nb = int(gib * (1 << 30))
+    out = {}
+
+    def rate(rd, wr, nt):
+        ms = ctx.stream_probe(rd, wr, nt, reps)
+        gbps = (rd + wr) / (ms * 1e-3) / 1e9
+        return {"read_bytes": rd, "write_bytes": wr, "ms": round(ms, 4), "GBps": round(gbps, 1),
+                "frac": round(gbps / HBM_PEAK_GBPS, 4)}
+    out["read"] = rate(nb, 0, False)
+    out["write"] = rate(0, nb, False)
+    out["write_nt"] = rate(0, nb, True)
+    out["copy"] = rate(nb, nb, False)
+    out["copy_nt"] = rate(nb, nb, True)
+    out["read1_write5"] = rate(nb // 5 // 16 * 16, 5 * (nb // 5 // 16 * 16), False)
+    out["read1_write5_nt"] = rate(nb // 5 // 16 * 16, 5 * (nb // 5 // 16 * 16), True)
+    return out
+
+
+def batched_roofline(out, ws):
+    """Nominal FFT + MAC flops of every product of the batch over the graph
+    replay time: the replay also holds the layout, count-sketch, inverse-FFT
+    and diagonal kernels, so this is a lower bound on the spectral kernels'
+    own rate."""
+    flop = sum(nominal_fft_mac_flop(w.m, w.b, w.d) for w in ws)
+    ms = out["graph_replay_ms"]
+    tf = flop / (ms * 1e-3) / 1e12
+    return {"kernel": "fft_mac (whole graph replay)", "bound": "alu", "achieved": round(tf, 3),
+            "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4),
+            "traffic": None, "flop_per_launch": flop, "avg_launch_ms": ms}
+
+
+# Steps and warm-up of the other benchmark workloads in the default run,
+# sized so that each is timed for well under a second.
+OTHER_CONFIGS = {1: (20, 3), 3: (10, 2), 4: (5, 1)}
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -387,6 +524,11 @@ def main():
 
     cmm.load()
     torch.cuda.init()
+    if args.stream_ceiling:
+        ctx = cmm.Context(0)
+        print(json.dumps({"stream_ceiling": stream_ceiling(ctx), "peak_GBps": HBM_PEAK_GBPS}), flush=True)
+        ctx.close()
+        return
     if args.workload == 5:
         ctx = cmm.Context(0)
         bres = run_batched(ctx, args.steps, args.warmup, not args.no_cpu)
@@ -395,83 +537,46 @@ def main():
             "metric": METRIC, "value": bres["value"], "unit": "GB/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": bres["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
-            "data": "synthetic", "config": {"workload": bres["workload"]}, "batched_form": bres}),
-            flush=True)
+            "data": "synthetic", "config": {"workload": bres["workload"]},
+            "roofline": bres["roofline"], "batched_form": bres}), flush=True)
         return
     w = W.make_workload(args.workload, dtype=args.dtype)
     if args.d is not None:
         w.d = args.d
-    n1, m, n3, b, d, K = w.n1, w.m, w.n3, w.b, w.d, w.K
     ctx = cmm.Context(0)
-    tuned = None
-    if args.geometry:
-        ctx.set_tuning(n1, m, n3, b, d, w.dtype, tuple(int(x) for x in args.geometry.split(",")))
-    elif not args.no_autotune:
-        # the library's one-time tuning of this size class (cached in the context)
-        t0 = time.perf_counter()
-        tu, tms = ctx.autotune(n1, m, n3, b, d, w.dtype)
-        tuned = {"log2c_kmax_csblocks": list(tu), "product_ms": round(tms, 4),
-                 "seconds": round(time.perf_counter() - t0, 2)}
-    r = run_timed(ctx, w, args.steps, args.warmup)
-    ms, kern, input_bytes = r["ms"], r["kern"], r["input_bytes"]
+    geometry = [int(x) for x in args.geometry.split(",")] if args.geometry else None
+    head, r = measure(ctx, w, args.steps, args.warmup, autotune=not args.no_autotune, geometry=geometry)
     sk, (oi, oj, ov) = r["sketch"], r["topk"]
-    value = input_bytes / (ms * 1e-3) / 1e9
-    fft_ms, fft_n = kern["fft_mac"]
-    fft_avg_ms = fft_ms / max(fft_n, 1)
-    flop = nominal_fft_mac_flop(m, b, d)
-    achieved_tflops = flop / (fft_avg_ms * 1e-3) / 1e12
-    cs_ms, cs_n = kern["countsketch"]
-    cs_avg_ms = cs_ms / max(cs_n, 1)
-    nb = expected_nonempty(n1, b) + expected_nonempty(n3, b)
-    cs_bytes = input_bytes + d * m * nb * 4
-    cs_gbps = cs_bytes / (cs_avg_ms * 1e-3) / 1e9
     c_gpu = sk.c()
-
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": head["value"],
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": w.dtype,
         "data": "synthetic",
         "config": {
-            "workload": (f"covariance n=m={n1} b={b} d={d} top-{K} i<j, diagonal subtracted"
-                         if w.mode == "upper" else
-                         f"{w.name} n1={n1} m={m} n3={n3} b={b} d={d} top-{K} {w.mode}"),
-            "n1": n1, "m": m, "n3": n3, "b": b, "d": d, "K": K, "topk_mode": w.mode,
-            "input_bytes": input_bytes,
-            "geometry": list(ctx.tuning(n1, m, n3, b, d, w.dtype)),
+            "workload": describe(w),
+            "n1": w.n1, "m": w.m, "n3": w.n3, "b": w.b, "d": w.d, "K": w.K, "topk_mode": w.mode,
+            "input_bytes": head["input_bytes"], "geometry": head["geometry"],
         },
-        "autotune": tuned,
-        "hbm_frac": round(value / HBM_PEAK_GBPS, 5),
-        "input_elements_per_s": round((n1 * m + m * n3) / (ms * 1e-3), 1),
-        "nominal_fft_gflops": round(flop / (ms * 1e-3) / 1e9, 1),
-        "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in kern.items()},
-        "roofline": {
-            "kernel": "fft_mac",
-            "kernels": ["k_fft_mac", "k_fft_mac_pair"],
-            "bound": "alu",
-            "achieved": round(achieved_tflops, 3),
-            "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": traffic_record(w, ctx.tuning(n1, m, n3, b, d, w.dtype)),
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "flop_per_launch": flop,
-            "avg_launch_ms": round(fft_avg_ms, 4),
-        },
-        "countsketch": {
-            "achieved": round(cs_gbps, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(cs_gbps / HBM_PEAK_GBPS, 4), "bytes_per_launch_pair": cs_bytes,
-            "avg_ms": round(cs_avg_ms, 4),
-        },
+        "roofline": head["roofline"],
     }
+    for k in ("autotune", "hbm_frac", "input_elements_per_s", "nominal_fft_gflops",
+              "ms_per_step_with_kernel_events", "kernel_ms_per_step", "countsketch", "decode_topk_ms"):
+        out[k] = head[k]
+    if not args.no_stream:
+        sc = stream_ceiling(ctx, gib=0.5, reps=5)
+        out["stream_ceiling"] = sc
+        best = max(sc["read1_write5"]["GBps"], sc["read1_write5_nt"]["GBps"])
+        out["countsketch"]["measured_ceiling_GBps"] = best
+        out["countsketch"]["frac_of_measured_ceiling"] = round(out["countsketch"]["achieved"] / best, 4)
     out["frobenius_bound"] = run_frobenius(ctx, w, args.steps)
     if not args.no_sparse and args.workload == 2:
         out["sparse_form"] = run_sparse(ctx, w, args.steps)
@@ -481,7 +586,7 @@ def main():
         out["find_significant"] = run_extract(ctx, w, out["frobenius_bound"]["median_X2"])
     c_ref = None
     if not args.no_cpu:
-        out["cpu_baseline"], out["parity"], c_ref = cpu_baseline(w, c_gpu, oi, oj, ov, input_bytes)
+        out["cpu_baseline"], out["parity"], c_ref = cpu_baseline(w, c_gpu, oi, oj, ov, head["input_bytes"])
         out["parity"]["planted_recall"] = planted_recall(w, oi, oj)
         fb = out["frobenius_bound"]
         fb["bound_over_true"] = round(fb["bound"] / out["parity"]["frobenius_norm_sq"], 3)
@@ -493,12 +598,35 @@ def main():
         # planted recall compared to this run's
         for dt in ("f32", "bf16", "fp8"):
             if dt != w.dtype:
-                out[f"{dt}_same_workload"] = compare_format(ctx, args, w, dt, c_ref, oi, oj, value)
+                out[f"{dt}_same_workload"] = compare_format(ctx, args, w, dt, c_ref, oi, oj, head["value"])
+    sk.free()
+    if not args.no_configs and args.workload == 2 and args.dtype is None and args.d is None:
+        # the other single-product benchmark workloads, each with its own
+        # tuning, timing, kernel times and roofline
+        out["configs"] = {}
+        for key, (st, wu) in OTHER_CONFIGS.items():
+            t0 = time.perf_counter()
+            wk = W.make_workload(key)
+            gen_s = time.perf_counter() - t0
+            res, rk = measure(ctx, wk, st, wu, autotune=not args.no_autotune)
+            oi_k, oj_k, _ = rk["topk"]
+            res["planted_recall"] = (planted_recall(wk, oi_k, oj_k) if wk.mode == "upper"
+                                     else spike_recall(wk, oi_k))
+            res["generate_s"] = round(gen_s, 2)
+            rk["sketch"].free()
+            out["configs"][wk.name] = res
+            del wk, rk
     if not args.no_batched:
         out["batched_form"] = run_batched(ctx, max(3, args.steps // 4), 1, not args.no_cpu)
-    sk.free()
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def spike_recall(w, oi):
+    """Transform workload: fraction of the planted spike rows found in the
+    per-column top-K."""
+    hits = sum(len(set(oi[j * w.K:(j + 1) * w.K].tolist()) & set(w.planted[j].tolist())) for j in range(w.n3))
+    return round(hits / (w.n3 * w.K), 4)
 
 
 def compare_format(ctx, args, w0, dtype, c_ref0, oi0, oj0, value0):

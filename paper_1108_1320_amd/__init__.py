@@ -112,6 +112,9 @@ def load(path: str | None = None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise RuntimeError(f"{p} is missing: build it with `python -m paper_1108_1320_amd.build`")
+    # torch first: libcmm.so then binds to the HIP runtime torch has loaded,
+    # so both share one runtime (device memory and streams pass between them)
+    import torch  # noqa: F401
     lib = C.CDLL(p)
     for name, (res, args) in _SIGS.items():
         f = getattr(lib, name)
