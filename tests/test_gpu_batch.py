@@ -344,3 +344,41 @@ def test_batched_covariance_workload_subset(cmm, ctx):
         for t in range(w.d):
             assert _rel_l2(c[t], c_ref[t]) <= REL_TOL, (q, t)
     bt.free()
+
+
+@pytest.mark.timeout(900)
+def test_batched_workload_every_product_vs_oracle(cmm, ctx):
+    """The batched benchmark workload as bench.py runs it (64 bf16 covariance
+    products, n = m log-uniform in [512, 8192], b = next power of two of 8n,
+    d = 5, diagonal subtracted, size classes autotuned, one graph replay):
+    every product's whole sketch against the oracle (per repetition rel. L2
+    and largest entry error <= 1e-5), and every product's top-(planted pairs)
+    over i < j against the oracle's inside the tolerance band."""
+    import oracle_runs as R
+    _say("case: batched workload, 64 products, every sketch and top-K vs the oracle")
+    ws = W.batched_workloads()
+    dev, probs = [], []
+    for w in ws:
+        A = _dev(w.At_store)
+        B = A.clone()
+        dev.append((A, B))
+        probs.append(cmm.problem(A, B, w.b, w.d, seed=w.seed, dtype=w.dtype, subtract_diag=True))
+    bt = cmm.Batch(ctx, probs, autotune=True, keep=dev)
+    bt.run()
+    res = bt.topk([w.K for w in ws], "upper")
+    worst_l2 = worst_inf = 0.0
+    for q, w in enumerate(ws):
+        c = bt.sketch(q).c()
+        A, B = W.dequantised(w)
+        tabs = O.hash_tables(O.hash_params(w.seed, w.d), w.n1, w.n3, w.b)
+        c_ref, _ = R.sketch(A, B, tabs, w.b, subtract_diag=True)
+        l2, inf = R.check_sketch(c, c_ref)
+        worst_l2, worst_inf = max(worst_l2, l2), max(worst_inf, inf)
+        oi, oj, ov = res[q]
+        ri, rj, rv = R.topk_upper(c_ref, tabs, w.n1, w.K)
+        R.band_check(oi, oj, ov, ri, rj, rv, abs(rv[-1]), R.decode_band(c, c_ref),
+                     lambda i, j: O.decode(c_ref, tabs, i, j))
+        if q % 16 == 15:
+            _say(f"  {q + 1} products checked")
+    _say(f"  worst rel L2 {worst_l2:.2e}, worst max|dc|/max|c| {worst_inf:.2e}")
+    bt.free()
