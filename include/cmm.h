@@ -219,6 +219,29 @@ int cmm_sketch_product_sparse(cmm_ctx* ctx, const int64_t* a_ptr, const int32_t*
                               const float* b_val, int64_t n1, int64_t m, int64_t n3, int64_t b,
                               int32_t d, uint64_t seed, uint32_t flags, cmm_sketch** out);
 
+/* Allocation-free form of cmm_sketch_product_ex, for callers that cannot
+ * allocate: code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc.  It computes the same sketch with the same kernels and
+ * writes c[d][b] (row-major float64) to the caller's DEVICE buffer c_out;
+ * it returns no handle.  It calls no hipMalloc/hipFree and no allocating
+ * library routine, creates no event, and does not wait for the stream: the
+ * result is ready when the context stream has passed the call.  All
+ * workspace (hash tables, bucket layout, count sketches, partial spectra,
+ * twiddles, hash parameters) lives in one device array of 256 MiB that the
+ * library holds on every device it runs on until the process ends; a
+ * product that needs more returns CMM_EUNSUPPORTED (call
+ * cmm_sketch_product_ex instead).  Every call on a device shares that
+ * device's array and leaves its contents behind (each call initialises what
+ * it reads), so calls that overlap on one device -- on two streams, or
+ * from two threads -- race and must be ordered by the caller.  The hash
+ * parameters come from `seed` (computed on the device by the rule above);
+ * flags: 0 or CMM_SUBTRACT_DIAG (n1 == n3).  Other arguments and errors as
+ * in cmm_sketch_product_ex. */
+int cmm_sketch_product_noalloc(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                               int64_t n1, int64_t m, int64_t n3, int32_t dtype,
+                               const float* scaleA, const float* scaleB, int64_t b, int32_t d,
+                               uint64_t seed, uint32_t flags, double* c_out);
+
 int cmm_sketch_free(cmm_sketch* sk);
 
 /* Dimensions of a sketch (any output pointer may be NULL). */

@@ -60,6 +60,8 @@ _SIGS = {
                                         _I64, _I32, _U64, _P, _U32, C.POINTER(_P)]),
     "cmm_sketch_product_tables": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P,
                                             _I64, _I32, _P, _P, _P, _P, _U32, C.POINTER(_P)]),
+    "cmm_sketch_product_noalloc": (C.c_int, [_P, _P, _I64, _P, _I64, _I64, _I64, _I64, _I32, _P, _P,
+                                             _I64, _I32, _U64, _U32, _P]),
     "cmm_sketch_free": (C.c_int, [_P]),
     "cmm_sketch_info": (C.c_int, [_P, C.POINTER(_I64), C.POINTER(_I64), C.POINTER(_I64),
                                   C.POINTER(_I64), C.POINTER(_I32)]),
@@ -518,6 +520,20 @@ def sketch_product(ctx: Context, At, B, b: int, d: int, seed: int = 0, dtype: st
     h = cmm_sketch_product_ex(ctx.handle, At, At.stride(0), B, B.stride(0), n1_, m_, n3_,
                               DTYPES[dtype], scaleA, scaleB, b, d, seed, hash_params, flags)
     return Sketch(h, ctx)
+
+
+def sketch_product_noalloc(ctx: Context, At, B, b: int, d: int, c_out, seed: int = 0, dtype: str = "f32",
+                           scaleA=None, scaleB=None, subtract_diag: bool = False,
+                           n1: int | None = None, n3: int | None = None, m: int | None = None):
+    """cmm_sketch_product_noalloc: the sketch of AB written into the float64
+    device tensor ``c_out`` (d x b) with no allocation; stream-ordered."""
+    m_ = m if m is not None else At.shape[0]
+    n1_ = n1 if n1 is not None else At.shape[1]
+    n3_ = n3 if n3 is not None else B.shape[1]
+    flags = CMM_SUBTRACT_DIAG if subtract_diag else 0
+    _check(load().cmm_sketch_product_noalloc(ctx.handle, _ptr(At), At.stride(0), _ptr(B), B.stride(0), n1_, m_,
+                                             n3_, DTYPES[dtype], _ptr(scaleA), _ptr(scaleB), b, d, seed, flags,
+                                             _ptr(c_out)), "cmm_sketch_product_noalloc", ctx.handle)
 
 
 def sketch_product_tables(ctx: Context, At, B, b, h1, s1, h2, s2, dtype="f32") -> Sketch:

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <initializer_list>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -128,6 +129,35 @@ int download_n(cmm_ctx* c, hipStream_t s, const Download* list, size_t n);
 
 bool valid_ctx(const cmm_ctx* c) { return c && c->magic == kCtxMagic; }
 bool valid_sketch(const cmm_sketch* s) { return s && s->magic == kSketchMagic && valid_ctx(s->ctx); }
+
+// ---- device scratch of the allocation-free product (cmm_sketch_product_noalloc)
+//
+// One array per device, held from the library's load until the process
+// ends.  Host code never passes `scratch` itself to a kernel or a copy (in
+// host code it names a host-side stand-in): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current when
+// a context is created there, and kept in g_scratch_dev.
+constexpr size_t kScratchBytes = size_t(256) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+void* g_scratch_dev[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Device address of `scratch` on `device` (the current device); looked up
+// once per device.
+void bind_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices || g_scratch_dev[device]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+    return;
+  }
+  g_scratch_dev[device] = p;
+}
 
 // ---- caching device allocator (stream-ordered reuse on the context stream)
 void* dalloc(cmm_ctx* c, size_t bytes) {
@@ -502,12 +532,13 @@ int download(cmm_ctx* c, hipStream_t s, std::initializer_list<Download> list) {
 // `c_out` (the sketch's own when null); `finish` also writes its float32 copy.
 int enqueue_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::Geometry& g,
                     const WsSpec& spec, const WsPtrs& ptr, const uint64_t* pdev, hipStream_t s,
-                    double* c_out = nullptr, bool finish = true) {
+                    double* c_out = nullptr, bool finish = true, double2* tw64_in = nullptr,
+                    float2* tw32_in = nullptr) {
   double* c64 = c_out ? c_out : sk->c64;
   cmm::SideDesc side[2];
   bind_sides(g, sk, op, spec, ptr, side);
-  double2* tw64; float2* tw32;
-  int rc = get_twiddles(c, g.b, &tw64, &tw32);
+  double2* tw64 = tw64_in; float2* tw32 = tw32_in;
+  int rc = tw64 && tw32 ? CMM_OK : get_twiddles(c, g.b, &tw64, &tw32);
   if (rc) return rc;
   rc = enqueue_layout(c, g, side, pdev, (int32_t*)ptr.p[W_OFLOW], s);
   if (rc) return rc;
@@ -1362,6 +1393,7 @@ int cmm_ctx_create(int device, void* hip_stream, cmm_ctx** out) {
     return CMM_EHIP;
   }
   if (const char* path = std::getenv("CMM_TUNE_CACHE")) load_tuning(c, path, true);
+  bind_scratch(device);   // device is current here
   *out = c;
   return CMM_OK;
 }
@@ -1489,6 +1521,70 @@ int cmm_sketch_product_tables(cmm_ctx* ctx, const void* A, int64_t lda, const vo
   if (valid_ctx(ctx) && (!h1 || !s1 || !h2 || !s2)) return fail(ctx, CMM_EINVAL, "tables are NULL");
   return product_common(ctx, A, lda, B, ldb, n1, m, n3, dtype, scaleA, scaleB, b, d, 0, nullptr,
                         h1, s1, h2, s2, flags, out);
+}
+
+int cmm_sketch_product_noalloc(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
+                               int64_t n1, int64_t m, int64_t n3, int32_t dtype,
+                               const float* scaleA, const float* scaleB, int64_t b, int32_t d,
+                               uint64_t seed, uint32_t flags, double* c_out) {
+  if (!valid_ctx(ctx)) return CMM_EINVAL;
+  int rc = check_operands(ctx, A, lda, B, ldb, n1, m, n3, dtype, b, d);
+  if (rc) return rc;
+  if (!c_out) return fail(ctx, CMM_EINVAL, "c_out is NULL");
+  if (flags & ~CMM_SUBTRACT_DIAG) return fail(ctx, CMM_EINVAL, "only CMM_SUBTRACT_DIAG is taken");
+  if ((flags & CMM_SUBTRACT_DIAG) && n1 != n3)
+    return fail(ctx, CMM_EINVAL, "CMM_SUBTRACT_DIAG needs n1 == n3");
+  if (dtype != CMM_FP8_E4M3 && (scaleA || scaleB))
+    return fail(ctx, CMM_EINVAL, "scales are only taken with CMM_FP8_E4M3");
+  CMM_HIP(ctx, hipSetDevice(ctx->device));
+  void* base = ctx->device < kMaxDevices ? g_scratch_dev[ctx->device] : nullptr;
+  if (!base) {
+    const hipError_t e = ctx->device < kMaxDevices ? g_scratch_err[ctx->device] : hipErrorInvalidDevice;
+    return fail(ctx, CMM_EHIP, std::string("device scratch unavailable: ") + hipGetErrorString(e));
+  }
+  // the layout takes its safe segment capacity (no overflow, so no host wait)
+  const cmm::Tuning tu = lookup_tuning(ctx, n1, m, n3, b, d, dtype);
+  const cmm::Geometry g = make_geometry(b, d, m, tu);
+  const WsSpec spec = ws_spec(g, n1, n3, true, flags);
+  // carve every buffer from the scratch array at 256-byte boundaries
+  size_t off = 0;
+  auto carve = [&](size_t bytes) -> size_t {
+    const size_t at = off;
+    off += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  size_t at[W_COUNT] = {};
+  for (int i = 0; i < W_COUNT; ++i) at[i] = carve(spec.count[i] * kElemSize[i]);
+  const size_t at_hs1 = carve(sizeof(int32_t) * (size_t)d * n1);
+  const size_t at_hs2 = carve(sizeof(int32_t) * (size_t)d * n3);
+  const size_t at_par = carve(sizeof(uint64_t) * (size_t)d * 8);
+  const size_t at_tw64 = carve(sizeof(double2) * (size_t)b);
+  const size_t at_tw32 = carve(sizeof(float2) * (size_t)b);
+  if (off > kScratchBytes)
+    return fail(ctx, CMM_EUNSUPPORTED,
+                "the allocation-free product needs " + std::to_string(off) + " bytes of device scratch; it holds " +
+                    std::to_string(kScratchBytes) + " (use cmm_sketch_product_ex)");
+  unsigned char* p = static_cast<unsigned char*>(base);
+  WsPtrs ptr;
+  for (int i = 0; i < W_COUNT; ++i) ptr.p[i] = spec.count[i] ? (void*)(p + at[i]) : nullptr;
+  cmm_sketch sk;   // a view: tables in the scratch, the result in c_out
+  sk.ctx = ctx; sk.n1 = n1; sk.m = m; sk.n3 = n3; sk.b = b; sk.d = d; sk.log2b = ilog2(b);
+  sk.hs1 = (int32_t*)(p + at_hs1);
+  sk.hs2 = (int32_t*)(p + at_hs2);
+  sk.c64 = c_out;
+  uint64_t* pdev = (uint64_t*)(p + at_par);
+  double2* tw64 = (double2*)(p + at_tw64);
+  float2* tw32 = (float2*)(p + at_tw32);
+  const bool prof = ctx->prof;
+  ctx->prof = false;   // no timing events: nothing is created here
+  if (cmm::launch_params_from_seed(seed, d, pdev, ctx->stream) != hipSuccess ||
+      cmm::launch_twiddles(tw64, tw32, b, ctx->stream) != hipSuccess)
+    rc = fail(ctx, CMM_EHIP, "parameter or twiddle launch failed");
+  const Operands op{A, lda, B, ldb, dtype, scaleA, scaleB, flags | CMM_ASYNC};
+  if (rc == CMM_OK) rc = enqueue_product(ctx, &sk, op, g, spec, ptr, pdev, ctx->stream, c_out, false, tw64, tw32);
+  ctx->prof = prof;
+  sk.magic = kDeadMagic;
+  return rc;
 }
 
 int cmm_sketch_free(cmm_sketch* sk) {

@@ -52,6 +52,15 @@ __device__ __forceinline__ uint64_t cw_hash61(uint64_t a, uint64_t x, uint64_t c
   return r;
 }
 
+// Output k (k >= 1) of SplitMix64 seeded with `seed` (Steele, Lea, Flood
+// 2014): the counter seed + k * gamma mixed by two xor-shift-multiply rounds.
+__device__ __forceinline__ uint64_t splitmix64_dev(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
 // OCP e4m3fn code (low 8 bits of v) to float32: bias 7, no infinities,
 // S.1111.111 is NaN, subnormals m * 2^-9.
 __device__ __forceinline__ float e4m3fn_to_f32(uint32_t v) {
@@ -163,6 +172,7 @@ struct Geometry {
 // ---- kernel launchers (stream-ordered, return hipError_t) ----
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t v, hipStream_t s);
 hipError_t launch_twiddles(double2* tw64, float2* tw32, int64_t b, hipStream_t s);
+hipError_t launch_params_from_seed(uint64_t seed, int d, uint64_t* out, hipStream_t s);
 hipError_t launch_hash(const uint64_t* params_dev, int side, const Geometry& g, SideDesc& sd,
                        hipStream_t s);
 hipError_t launch_count(const Geometry& g, SideDesc& sd, hipStream_t s);

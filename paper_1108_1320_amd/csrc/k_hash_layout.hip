@@ -43,6 +43,24 @@ hipError_t launch_twiddles(double2* tw64, float2* tw32, int64_t b, hipStream_t s
   return hipGetLastError();
 }
 
+// Hash parameters of every repetition t and function f (h1, s1, h2, s2)
+// from the SplitMix64 stream of `seed`, by the rule the host uses: thread
+// q = 4t + f reads outputs z_{2q+1}, z_{2q+2} and writes
+// a = 1 + z mod (2^61 - 2), c = z' mod (2^61 - 1) to out[2q], out[2q+1].
+__global__ void k_params_from_seed(uint64_t seed, int d, uint64_t* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 4 * d) return;
+  const uint64_t za = splitmix64_dev(seed, 2 * (uint64_t)q + 1);
+  const uint64_t zc = splitmix64_dev(seed, 2 * (uint64_t)q + 2);
+  out[2 * q] = 1 + za % (CMM_P61 - 1);
+  out[2 * q + 1] = zc % CMM_P61;
+}
+
+hipError_t launch_params_from_seed(uint64_t seed, int d, uint64_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_params_from_seed, dim3((4 * d + 255) / 256), dim3(256), 0, s, seed, d, out);
+  return hipGetLastError();
+}
+
 // hs[t][x] = (h(x) << 1) | (s(x) == -1) for x < n, every repetition t.
 __global__ void k_hash(const uint64_t* __restrict__ params, int side, int d, int n,
                        uint64_t bmask, int32_t* __restrict__ hs) {

@@ -7,15 +7,6 @@
 
 namespace cmm {
 
-// Output k (k >= 1) of SplitMix64 seeded with `seed` (Steele, Lea, Flood
-// 2014): the counter seed + k * gamma mixed by two xor-shift-multiply rounds.
-__device__ __forceinline__ uint64_t splitmix64_dev(uint64_t seed, uint64_t k) {
-  uint64_t z = seed + k * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 // out[x] = float(1 + (z_{offset + x + 1} >> 11) 2^-53) * (scale ? scale[x] : 1)
 __global__ void k_nnz_weights(uint64_t seed, uint64_t offset, int n, const float* __restrict__ scale,
                               float* __restrict__ out) {
