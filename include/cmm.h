@@ -428,7 +428,14 @@ int cmm_estimate_batch(const cmm_sketch* sk, const int64_t* i, const int64_t* j,
  * (ties between equal magnitudes therefore resolve to the smaller index).
  * Outputs are host arrays of K entries (n3*K for CMM_TOPK_PER_COLUMN, column
  * j's results at [j*K, (j+1)*K)).  The estimates are decoded on the device
- * and never stored as a whole matrix. */
+ * and never stored as a whole matrix.
+ * Limits (CMM_EUNSUPPORTED): for CMM_TOPK_ALL and CMM_TOPK_UPPER, K <= 2048
+ * (the last ranking sorts at most 4096 candidates in one block's LDS) and
+ * at most 4096 estimates may tie at the K-th magnitude (ties are common
+ * only with d = 1, where every entry of a bucket has the same magnitude).
+ * Section 4's goal of the b/kappa largest entries exceeds 2048 at b >= 2^16
+ * with kappa <= 32; that extraction is cmm_find_significant, which has no
+ * such cap.  CMM_TOPK_PER_COLUMN takes any K up to n1. */
 int cmm_topk(const cmm_sketch* sk, int32_t K, int32_t mode, int64_t* out_i, int64_t* out_j,
              float* out_val);
 

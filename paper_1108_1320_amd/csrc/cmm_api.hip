@@ -560,7 +560,7 @@ int enqueue_product(cmm_ctx* c, cmm_sketch* sk, const Operands& op, const cmm::G
       CMM_HIP(c, cmm::launch_diag(op.dtype, side[0], side[1], g.m, n, (double*)ptr.p[W_PARTIAL],
                                   spec.kch, (double*)ptr.p[W_DIAG], s));
       CMM_HIP(c, cmm::launch_sub_diag(g, sk->hs1, sk->hs2, (int)sk->n1, (int)sk->n3,
-                                      (double*)ptr.p[W_DIAG], n, c64, s));
+                                      (double*)ptr.p[W_DIAG], n, c64, ptr.p[W_WORK0], s));
     }
     if (finish) CMM_HIP(c, cmm::launch_to_f32(sk->c64, sk->c32, (int64_t)g.d * g.b, s));
   }
@@ -1650,7 +1650,11 @@ int cmm_sketch_subtract_diagonal(cmm_sketch* sk, const double* diag, int64_t len
   if (!diag || len < 0 || len > std::min(sk->n1, sk->n3)) return fail(c, CMM_EINVAL, "bad diag");
   if (len == 0) return CMM_OK;
   cmm::Geometry g = make_geometry(sk->b, sk->d, sk->m, cmm::Tuning());
-  CMM_HIP(c, cmm::launch_sub_diag(g, sk->hs1, sk->hs2, (int)sk->n1, (int)sk->n3, diag, (int)len, sk->c64, c->stream));
+  Work w(c);
+  void* tmp = w.get<double2>((size_t)sk->d * sk->b);
+  if (!tmp) return fail(c, CMM_ENOMEM, "workspace allocation failed");
+  CMM_HIP(c, cmm::launch_sub_diag(g, sk->hs1, sk->hs2, (int)sk->n1, (int)sk->n3, diag, (int)len, sk->c64,
+                                  tmp, c->stream));
   CMM_HIP(c, cmm::launch_to_f32(sk->c64, sk->c32, sk->d * sk->b, c->stream));
   CMM_HIP(c, hipStreamSynchronize(c->stream));
   return CMM_OK;
@@ -2062,7 +2066,8 @@ int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B
                                       (double2*)ptr.p[W_WORK1], tw64, ctmp, s));
         if (diagm) {
           CMM_HIP(ctx, cmm::launch_code_mask_diag((int)n1, Ls[q], r, (const double*)ptr.p[W_DIAG], diagm, s));
-          CMM_HIP(ctx, cmm::launch_sub_diag(g, sk->hs1, sk->hs2, (int)n1, (int)n3, diagm, (int)n1, ctmp, s));
+          CMM_HIP(ctx, cmm::launch_sub_diag(g, sk->hs1, sk->hs2, (int)n1, (int)n3, diagm, (int)n1, ctmp,
+                                            ptr.p[W_WORK0], s));
         }
         CMM_HIP(ctx, cmm::launch_to_f32(ctmp, cr + slot * db, db, s));
         return CMM_OK;

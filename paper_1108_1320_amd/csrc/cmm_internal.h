@@ -195,8 +195,11 @@ hipError_t launch_ifft(const Geometry& g, const float2* Ppart, double2* work0, d
                        const double2* tw64, double* c64, hipStream_t s);
 hipError_t launch_diag(int dtype, const SideDesc& a, const SideDesc& bside, int m, int n,
                        double* partial, int kchunks, double* diag, hipStream_t s);
+// tmp: device scratch of at least 16 * d * b bytes (the inverse FFT's work
+// buffer after the inverse FFT)
 hipError_t launch_sub_diag(const Geometry& g, const int32_t* hs1, const int32_t* hs2, int n1,
-                           int n3, const double* diag, int len, double* c64, hipStream_t s);
+                           int n3, const double* diag, int len, double* c64, void* tmp,
+                           hipStream_t s);
 hipError_t launch_to_f32(const double* c64, float* c32, int64_t count, hipStream_t s);
 hipError_t launch_add_f64(double* dst, const double* src, int64_t count, hipStream_t s);
 hipError_t launch_ams_signs(const uint64_t* params, int d, int side, int n, uint64_t* mask,

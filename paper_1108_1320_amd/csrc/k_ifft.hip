@@ -203,32 +203,34 @@ __global__ __launch_bounds__(64) void k_diag_reduce(const double* __restrict__ p
   diag[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
-// diag[i] = sum_k A[i,k] B[k,i] for sparse A (by columns k) and B (by rows
-// k): one block per k stages column k of A in LDS (zeroed, then scattered)
-// and adds the float64 products with the entries of row k of B (float64
-// atomics: the summation order is not fixed).
+// partial[kc][j] = sum over k in chunk kc of A[j,k] B[k,j] for sparse A (by
+// columns k) and B (by rows k): block kc takes its k one after the other,
+// stages column k of A in LDS (zeroed, then scattered) and adds the float64
+// products with the entries of row k of B into its own partial row.  Within
+// one k the entries of row k of B have distinct columns, so no two threads
+// touch one j; successive k are separated by block barriers.  The partial
+// rows are then summed in a fixed order (k_diag_reduce), so the diagonal
+// does not depend on scheduling.
 __global__ void k_diag_sparse(const int64_t* __restrict__ aptr, const int32_t* __restrict__ aidx,
                               const float* __restrict__ aval, const int64_t* __restrict__ bptr,
                               const int32_t* __restrict__ bidx, const float* __restrict__ bval,
-                              int m, int n, double* __restrict__ diag) {
+                              int m, int n, int kchunks, double* __restrict__ partial) {
   extern __shared__ float col[];
-  for (int k = blockIdx.x; k < m; k += gridDim.x) {
+  const int kc = blockIdx.x;
+  double* pr = partial + (int64_t)kc * n;
+  for (int x = threadIdx.x; x < n; x += blockDim.x) pr[x] = 0.0;
+  const int k0 = (int)((int64_t)m * kc / kchunks), k1 = (int)((int64_t)m * (kc + 1) / kchunks);
+  for (int k = k0; k < k1; ++k) {
     for (int x = threadIdx.x; x < n; x += blockDim.x) col[x] = 0.0f;
     __syncthreads();
     for (int64_t e = aptr[k] + threadIdx.x; e < aptr[k + 1]; e += blockDim.x) col[aidx[e]] = aval[e];
     __syncthreads();
     for (int64_t e = bptr[k] + threadIdx.x; e < bptr[k + 1]; e += blockDim.x) {
       const int j = bidx[e];
-      if (j < n && col[j] != 0.0f) atomicAdd(&diag[j], (double)col[j] * (double)bval[e]);
+      if (j < n && col[j] != 0.0f) pr[j] += (double)col[j] * (double)bval[e];
     }
     __syncthreads();
   }
-}
-
-__global__ void k_zero_f64(double* __restrict__ p, int64_t count) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0;
 }
 
 // Sparse operand check: offsets non-decreasing from 0, every index in [0, n).
@@ -261,9 +263,12 @@ hipError_t prepare_sparse() {
 hipError_t launch_diag(int dtype, const SideDesc& a, const SideDesc& bs, int m, int n,
                        double* partial, int kchunks, double* diag, hipStream_t s) {
   if (dtype == kSparseF32) {
-    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(n)), dim3(256), 0, s, diag, (int64_t)n);
-    hipLaunchKernelGGL(k_diag_sparse, dim3(m < 4096 ? m : 4096), dim3(256), (size_t)n * sizeof(float), s,
-                       a.sptr, a.sidx, (const float*)a.X, bs.sptr, bs.sidx, (const float*)bs.X, m, n, diag);
+    hipLaunchKernelGGL(k_diag_sparse, dim3(kchunks), dim3(256), (size_t)n * sizeof(float), s,
+                       a.sptr, a.sidx, (const float*)a.X, bs.sptr, bs.sidx, (const float*)bs.X, m, n,
+                       kchunks, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_diag_reduce, dim3((n + 63) / 64), dim3(64), 0, s, partial, n, kchunks, diag);
     return hipGetLastError();
   }
   dim3 grid((n + 255) / 256, kchunks);
@@ -279,26 +284,100 @@ hipError_t launch_diag(int dtype, const SideDesc& a, const SideDesc& bs, int m, 
   return hipGetLastError();
 }
 
-// c_t[(h1(i) + h2(i)) mod b] -= s1(i) s2(i) diag[i]
-__global__ void k_sub_diag(const int32_t* __restrict__ hs1, const int32_t* __restrict__ hs2,
-                           int n1, int n3, const double* __restrict__ diag, int len, int d,
-                           int64_t b, double* __restrict__ c64) {
+// c_t[(h1(i) + h2(i)) mod b] -= s1(i) s2(i) diag[i] for i < len, the same
+// for every run: several i can share a bucket, so their contributions are
+// summed exactly in 64-bit fixed point (integer sums do not depend on the
+// order of the adds) and one thread per touched bucket, that of its
+// smallest i, applies the sum.  The shift s keeps len * max|diag| * 2^s
+// below 2^62; each contribution is rounded to a multiple of 2^-s, an error
+// below len * max|diag| * 2^-63.  tmp holds acc[d * b] (int64), owner[d * b]
+// (int32) and the shift (int32): at least 16 d b bytes.
+__global__ __launch_bounds__(1024) void k_diag_shift(const double* __restrict__ diag, int len,
+                                                     int* __restrict__ shift) {
+  __shared__ double wmax[16];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < len; i += blockDim.x) mx = fmax(mx, fabs(diag[i]));
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) mx = fmax(mx, wmax[w]);
+    int e = 0;
+    (void)frexp(mx, &e);                 // mx < 2^e
+    int l = 0;
+    while ((1 << l) < len) ++l;          // len <= 2^l
+    *shift = mx > 0.0 ? 62 - e - l : 0;
+  }
+}
+
+__device__ __forceinline__ int64_t diag_bucket(const int32_t* hs1, const int32_t* hs2, int n1, int n3,
+                                               int t, int i, int64_t b, bool* neg) {
+  const int32_t a = hs1[(int64_t)t * n1 + i], c = hs2[(int64_t)t * n3 + i];
+  *neg = ((a ^ c) & 1) != 0;      // s1(i) s2(i) = -1
+  return (int64_t)t * b + ((int64_t)((a >> 1) + (c >> 1)) & (b - 1));
+}
+
+__global__ void k_sub_diag_init(const int32_t* __restrict__ hs1, const int32_t* __restrict__ hs2,
+                                int n1, int n3, int len, int d, int64_t b,
+                                long long* __restrict__ acc, int* __restrict__ owner) {
   const int64_t total = (int64_t)d * len;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    const int t = (int)(idx / len);
-    const int i = (int)(idx - (int64_t)t * len);
-    const int32_t a = hs1[(int64_t)t * n1 + i], c = hs2[(int64_t)t * n3 + i];
-    const int64_t u = (int64_t)((a >> 1) + (c >> 1)) & (b - 1);
-    const double v = ((a ^ c) & 1) ? diag[i] : -diag[i];
-    atomicAdd(&c64[(int64_t)t * b + u], v);
+    const int t = (int)(idx / len), i = (int)(idx - (int64_t)t * len);
+    bool neg;
+    const int64_t u = diag_bucket(hs1, hs2, n1, n3, t, i, b, &neg);
+    acc[u] = 0;
+    owner[u] = 0x7FFFFFFF;
+  }
+}
+
+__global__ void k_sub_diag_add(const int32_t* __restrict__ hs1, const int32_t* __restrict__ hs2,
+                               int n1, int n3, const double* __restrict__ diag, int len, int d,
+                               int64_t b, const int* __restrict__ shift, long long* __restrict__ acc,
+                               int* __restrict__ owner) {
+  const int64_t total = (int64_t)d * len;
+  const int sh = *shift;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(idx / len), i = (int)(idx - (int64_t)t * len);
+    bool neg;
+    const int64_t u = diag_bucket(hs1, hs2, n1, n3, t, i, b, &neg);
+    const double v = neg ? diag[i] : -diag[i];    // the amount added to c_t[u]
+    const long long q = __double2ll_rn(ldexp(v, sh));
+    atomicAdd(reinterpret_cast<unsigned long long*>(&acc[u]), (unsigned long long)q);
+    atomicMin(&owner[u], i);
+  }
+}
+
+__global__ void k_sub_diag_apply(const int32_t* __restrict__ hs1, const int32_t* __restrict__ hs2,
+                                 int n1, int n3, int len, int d, int64_t b,
+                                 const int* __restrict__ shift, const long long* __restrict__ acc,
+                                 const int* __restrict__ owner, double* __restrict__ c64) {
+  const int64_t total = (int64_t)d * len;
+  const int sh = *shift;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(idx / len), i = (int)(idx - (int64_t)t * len);
+    bool neg;
+    const int64_t u = diag_bucket(hs1, hs2, n1, n3, t, i, b, &neg);
+    if (owner[u] == i) c64[u] += ldexp((double)acc[u], -sh);
   }
 }
 
 hipError_t launch_sub_diag(const Geometry& g, const int32_t* hs1, const int32_t* hs2, int n1,
-                           int n3, const double* diag, int len, double* c64, hipStream_t s) {
-  hipLaunchKernelGGL(k_sub_diag, dim3(grid_for((int64_t)g.d * len)), dim3(256), 0, s, hs1, hs2,
-                     n1, n3, diag, len, g.d, g.b, c64);
+                           int n3, const double* diag, int len, double* c64, void* tmp,
+                           hipStream_t s) {
+  const int64_t db = (int64_t)g.d * g.b;
+  long long* acc = static_cast<long long*>(tmp);
+  int* owner = reinterpret_cast<int*>(acc + db);
+  int* shift = owner + db;
+  const unsigned grid = grid_for((int64_t)g.d * len);
+  hipLaunchKernelGGL(k_diag_shift, dim3(1), dim3(1024), 0, s, diag, len, shift);
+  hipLaunchKernelGGL(k_sub_diag_init, dim3(grid), dim3(256), 0, s, hs1, hs2, n1, n3, len, g.d, g.b, acc, owner);
+  hipLaunchKernelGGL(k_sub_diag_add, dim3(grid), dim3(256), 0, s, hs1, hs2, n1, n3, diag, len, g.d,
+                     g.b, shift, acc, owner);
+  hipLaunchKernelGGL(k_sub_diag_apply, dim3(grid), dim3(256), 0, s, hs1, hs2, n1, n3, len, g.d, g.b,
+                     shift, acc, owner, c64);
   return hipGetLastError();
 }
 

@@ -175,6 +175,37 @@ def test_subtract_diagonal_parity(cmm, ctx):
         assert _rel_l2(c_gpu[t], c_ref[t]) <= REL_TOL
 
 
+def test_subtract_diagonal_deterministic_with_collisions(cmm, ctx):
+    """3000 diagonal entries into 256 buckets: each bucket takes about a
+    dozen of them per repetition.  Two runs give the same bits, the result
+    matches the oracle, and subtracting the host-computed float64 diagonal
+    from the plain sketch (cmm_sketch_subtract_diagonal) agrees with it."""
+    import torch
+    _say("case: diagonal subtraction with many collisions, determinism")
+    g = np.random.default_rng(12)
+    n, m, b, d = 3000, 50, 256, 4
+    X = g.standard_normal((m, n)).astype(np.float32)
+    dX = _dev(X)
+    runs = [cmm.sketch_product(ctx, dX, dX.clone(), b, d, seed=31, subtract_diag=True) for _ in range(3)]
+    cs = [r.c() for r in runs]
+    for c in cs[1:]:
+        np.testing.assert_array_equal(c, cs[0])
+    c_ref, _, _ = _oracle_c(X, X, b, d, 31, subtract_diag=True)
+    for t in range(d):
+        assert _rel_l2(cs[0][t], c_ref[t]) <= REL_TOL
+    plain = cmm.sketch_product(ctx, dX, dX.clone(), b, d, seed=31)
+    Xd = X.astype(np.float64)
+    diag = torch.from_numpy(np.einsum("ki,ki->i", Xd, Xd)).cuda()
+    plain.subtract_diagonal(diag)
+    cp = plain.c()
+    assert np.abs(cp - cs[0]).max() <= 1e-9 * np.abs(cs[0]).max()
+    again = cmm.sketch_product(ctx, dX, dX.clone(), b, d, seed=31)
+    again.subtract_diagonal(diag)
+    np.testing.assert_array_equal(again.c(), cp)
+    for r in runs + [plain, again]:
+        r.free()
+
+
 # ----------------------------------------------------- decoding and top-K
 
 def _tables_np(tabs):
