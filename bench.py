@@ -88,6 +88,9 @@ def parse():
     p.add_argument("--stream-ceiling", action="store_true",
                    help="only measure plain HBM streams (read, write, copy, 1:5 read:write; ordinary "
                         "and streaming stores) and print them")
+    p.add_argument("--replay-trace", type=int, default=0, metavar="N",
+                   help="build the batched workload's graph, then run N graph replays 100 ms apart "
+                        "(no top-K) so that a kernel trace can separate one replay's dispatches")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -440,19 +443,20 @@ def run_extract(ctx, w, median_x2):
 
 def traffic_record(w, geometry):
     """HBM bytes per spectral step (both fft_mac kernels) from the committed
-    rocprofv3 counter summary, if it was taken on this workload at this
-    geometry (log2c, kmax, cs_blocks) and the kernel source has not changed
-    since (else None)."""
+    rocprofv3 counter summary (profiles/fft_mac_traffic.json), if it holds a
+    record of this workload at this geometry (log2c, kmax, cs_blocks) and the
+    kernel source has not changed since the counters were taken (else None)."""
     import hashlib
-    rec_path = os.path.join(ROOT, "profiles", "fft_mac_cov4096_f32_traffic.json")
+    rec_path = os.path.join(ROOT, "profiles", "fft_mac_traffic.json")
     src = os.path.join(ROOT, "paper_1108_1320_amd", "csrc", "k_fft_mac.hip")
-    if not (w.name == "covariance-4096" and w.dtype == "f32" and os.path.exists(rec_path)):
+    if not os.path.exists(rec_path) or w.dtype != {"covariance-256": "f32", "covariance-4096": "f32",
+                                                   "dct-8192": "bf16", "covariance-16384": "fp8"}.get(w.name):
         return None
     rec = json.load(open(rec_path))
-    if rec.get("source_sha256_16") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
+    if rec.get("fft_mac_source_sha256_16") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
         return None
     for r in rec.get("records", []):
-        if list(r["geometry"]) == list(geometry):
+        if r["workload"] == w.name and list(r["geometry"]) == list(geometry):
             return r["read_bytes"] + r["write_bytes"]
     return None
 
@@ -518,12 +522,39 @@ def main():
               "(the sketch would shard over k with one all-reduce of c; not built).", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     import paper_1108_1320_amd as cmm
     import workloads as W
 
     cmm.load()
     torch.cuda.init()
+    if args.replay_trace:
+        ctx = cmm.Context(0)
+        ws = W.batched_workloads()
+        dev, probs = [], []
+        for w in ws:
+            A = torch.from_numpy(np.ascontiguousarray(w.At_store)).cuda()
+            B = A.clone()
+            dev.append((A, B))
+            probs.append(cmm.problem(A, B, w.b, w.d, seed=w.seed, dtype=w.dtype, subtract_diag=True))
+        bt = cmm.Batch(ctx, probs, autotune=True, keep=dev)
+        bt.run()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(args.replay_trace):
+            time.sleep(0.1)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            bt.run(asynchronous=True)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        print(json.dumps({"replays": args.replay_trace, "replay_ms": [round(x, 3) for x in ms],
+                          "products": len(ws)}), flush=True)
+        bt.free()
+        ctx.close()
+        return
     if args.stream_ceiling:
         ctx = cmm.Context(0)
         print(json.dumps({"stream_ceiling": stream_ceiling(ctx), "peak_GBps": HBM_PEAK_GBPS}), flush=True)

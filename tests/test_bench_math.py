@@ -40,20 +40,23 @@ def test_expected_nonempty_matches_simulation():
 
 def test_traffic_record_only_for_its_workload():
     import json
-    rec = os.path.join(ROOT, "profiles", "fft_mac_cov4096_f32_traffic.json")
-    assert os.path.exists(rec)
-    geos = [tuple(r["geometry"]) for r in json.load(open(rec))["records"]]
-    assert geos
-    w = W.make_workload(1)
-    assert bench.traffic_record(w, geos[0]) is None  # recorded for covariance 4096 f32 only
-    w2 = W.make_workload(2)
-    assert bench.traffic_record(w2, (9, 7, 5)) is None  # no record at another geometry
     import hashlib
+    rec = os.path.join(ROOT, "profiles", "fft_mac_traffic.json")
+    assert os.path.exists(rec)
+    data = json.load(open(rec))
+    recs = [(r["workload"], tuple(r["geometry"])) for r in data["records"]]
+    assert recs
     src = os.path.join(ROOT, "paper_1108_1320_amd", "csrc", "k_fft_mac.hip")
-    fresh = json.load(open(rec))["source_sha256_16"] == hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    for g in geos:              # present for each recorded geometry while the source is unchanged
-        t = bench.traffic_record(w2, g)
+    fresh = data["fft_mac_source_sha256_16"] == hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    from types import SimpleNamespace          # the record is keyed by name and format only
+    dtype_of = {c["name"]: c["dtype"] for c in W.CONFIGS.values()}
+    for name, geo in recs:
+        w = SimpleNamespace(name=name, dtype=dtype_of[name])
+        t = bench.traffic_record(w, geo)          # present while the source is unchanged
         assert (t > 0) if fresh else (t is None)
+        assert bench.traffic_record(w, (9, 7, 5)) is None   # no record at another geometry
+        other = SimpleNamespace(name=name, dtype="bf16" if dtype_of[name] != "bf16" else "f32")
+        assert bench.traffic_record(other, geo) is None     # same workload, other operand format
 
 
 def test_multi_gpu_request_refused():
