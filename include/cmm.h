@@ -391,20 +391,24 @@ int cmm_estimate_nnz(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, in
 /* FINDSIGNIFICANTENTRIES(delta): positions (i, j) of significant entries of
  * AB.  Besides the sketch of AB, the library computes with the same hash
  * functions the sketches of the submatrix products of eq. (3),
- * (I_{E_r} A) B for the 2 L1 bits of the row code and A (B I_{E_r}) for the
- * 2 L3 bits of the column code, where E(x) = bits(x) || not bits(x) over
- * L = max(1, ceil(log2 n)) bits (the paper's expander code is not given;
- * this complement code detects, not corrects, errors).  For every
- * repetition t and bucket k the bit string [|p^(t,r)[k]| > delta/2] is
- * decoded into (i, j), or rejected unless every bit pair is complementary;
- * positions decoded in at least d/2 repetitions are returned, sorted by
+ * (I_{E_r} A) B for the 63 bits of the row code and A (B I_{E_r}) for the
+ * 63 bits of the column code.  E is the binary BCH code of length 63 with
+ * designed distance 23 (16 information bits; any 11 bit errors are
+ * corrected): index x is the systematic codeword of message x + 1, so
+ * n1, n3 <= 65535.  (The paper names an expander code; any code that
+ * corrects a constant fraction of errors serves, and this one corrects
+ * 11/63 of them.)  For every repetition t and bucket k the two 63-bit strings
+ * [|p^(t,r)[k]| > delta/2] are decoded (syndromes, Berlekamp-Massey, Chien
+ * search); a string that does not decode, or decodes to message 0 (a bucket
+ * without a significant entry thresholds to weight <= 11), gives nothing.
+ * Positions decoded in at least d/2 repetitions are returned, sorted by
  * i*n3 + j, at most `cap` of them in out_i/out_j (host arrays), with
  * *out_count the full number (call again with a larger cap if it exceeds
  * cap).  Operands, dtype, scales, b, d, seed as in cmm_sketch_product_ex;
  * flags: CMM_SUBTRACT_DIAG (the product with a zero diagonal).  main_out,
  * if non-NULL, receives the sketch of AB itself (for DECOMPRESS of the
  * returned positions); free it with cmm_sketch_free().  The work is
- * 2 (L1 + L3) + 1 sketch products (Section 4: a factor O(lg n) more time for
+ * 2 * 63 + 1 sketch products (Section 4: a factor O(lg n) more time for
  * compression). */
 int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
                          int64_t n1, int64_t m, int64_t n3, int32_t dtype, const float* scaleA,

@@ -454,52 +454,196 @@ def estimate_nnz(A: np.ndarray, B: np.ndarray, d: int, seed: int, zero_rel: floa
 # ---------------------------------------------------------------------------
 
 # Reading: the paper's expander code is not given.  The code used is the
-# complement code E(x) = bits(x) || not bits(x) over L = max(1, ceil(log2 n))
-# bits, l = 2L: every codeword has weight L, DECODE accepts a string only if
-# each pair (bit q, bit q + L) is (1, 0) or (0, 1) and fails otherwise (an
-# empty bucket, all bits 0, never decodes), and the d/2 vote over the
-# repetitions removes wrongly decoded positions.
+# binary BCH code of length 63 with designed distance 23 (Bose, Ray-Chaudhuri,
+# Hocquenghem): 16 information bits, minimum distance >= 23, so every word
+# within Hamming distance t = 11 of a codeword decodes to it (a fraction
+# delta = 11/63 of the 63 bits).  Index x is encoded as the systematic
+# codeword of the message x + 1 (message 0, the all-zero word, is kept for
+# "nothing here": a bucket without a significant entry thresholds to a string
+# of low weight, which decodes to message 0 or fails).  Indices need
+# x + 1 < 2^16.  Decoding: syndromes S_1..S_22 in GF(2^6), Berlekamp-Massey
+# for the error locator, a search over the 63 positions for its roots
+# (Chien search); more than 11 errors, or a locator whose roots are not all
+# distinct positions, fails.
+
+BCH_N, BCH_K, BCH_T = 63, 16, 11
+GF64_POLY = 0b1000011          # x^6 + x + 1, primitive over GF(2)
 
 
-def code_bits(n: int) -> int:
-    """L = number of information bits for indices 0..n-1."""
-    return max(1, int(np.ceil(np.log2(n)))) if n > 1 else 1
+def _gf64_tables():
+    exp = [0] * 126
+    log = [0] * 64
+    v = 1
+    for i in range(63):
+        exp[i] = exp[i + 63] = v
+        log[v] = i
+        v <<= 1
+        if v & 64:
+            v ^= GF64_POLY
+    return exp, log
 
 
-def code_encode(x: int, L: int) -> list[int]:
-    """E(x) = bits(x) (least significant first) followed by their complements."""
-    bits = [(x >> q) & 1 for q in range(L)]
-    return bits + [1 - v for v in bits]
+_GF_EXP, _GF_LOG = _gf64_tables()
 
 
-def code_decode(s, L: int):
-    """x from a bit string of length 2L, or None if some pair is not (1,0)/(0,1)."""
-    x = 0
-    for q in range(L):
-        a, c = int(s[q]), int(s[q + L])
-        if a == c:
-            return None
-        x |= a << q
-    return x
+def _gf_mul(a: int, b: int) -> int:
+    return 0 if a == 0 or b == 0 else _GF_EXP[_GF_LOG[a] + _GF_LOG[b]]
+
+
+def _poly2_mul(a: int, b: int) -> int:
+    """Product of two GF(2) polynomials held as bit masks (bit i = x^i)."""
+    out = 0
+    while b:
+        if b & 1:
+            out ^= a
+        a <<= 1
+        b >>= 1
+    return out
+
+
+def _poly2_mod(a: int, m: int) -> int:
+    dm = m.bit_length() - 1
+    while a and a.bit_length() - 1 >= dm:
+        a ^= m << (a.bit_length() - 1 - dm)
+    return a
+
+
+def _minimal_poly(i: int) -> int:
+    """Minimal polynomial over GF(2) of alpha^i: the product of (x - alpha^j)
+    over the cyclotomic coset {i, 2i, 4i, ...} mod 63 (coefficients come out
+    in GF(2))."""
+    coset, j = [], i % 63
+    while j not in coset:
+        coset.append(j)
+        j = (2 * j) % 63
+    poly = [1]                      # coefficients in GF(64), lowest degree first
+    for j in coset:
+        root = _GF_EXP[j]
+        nxt = [0] * (len(poly) + 1)
+        for d, c in enumerate(poly):
+            nxt[d + 1] ^= c                      # c x^(d+1)
+            nxt[d] ^= _gf_mul(c, root)           # c root x^d (minus = plus)
+        poly = nxt
+    assert all(c in (0, 1) for c in poly)
+    return sum(c << d for d, c in enumerate(poly))
+
+
+def bch_generator() -> int:
+    """Generator polynomial (bit mask) of the narrow-sense BCH code of length
+    63 with roots alpha^1 .. alpha^22: the product of the distinct minimal
+    polynomials of those roots (degree 47)."""
+    g, seen = 1, set()
+    for i in range(1, 2 * BCH_T + 1):
+        mp = _minimal_poly(i)
+        if mp not in seen:
+            seen.add(mp)
+            g = _poly2_mul(g, mp)
+    return g
+
+
+BCH_G = bch_generator()
+
+
+def bch_encode(msg: int) -> int:
+    """Systematic codeword (63-bit mask): message bits at positions 47..62,
+    parity = (msg x^47) mod g at positions 0..46."""
+    shifted = msg << (BCH_N - BCH_K)
+    return shifted | _poly2_mod(shifted, BCH_G)
+
+
+def bch_decode(word: int):
+    """The message of the codeword within distance 11 of ``word`` (63-bit
+    mask), or None when the decoder finds no such codeword."""
+    synd = []
+    for j in range(1, 2 * BCH_T + 1):
+        s = 0
+        for p in range(BCH_N):
+            if word >> p & 1:
+                s ^= _GF_EXP[(j * p) % 63]
+        synd.append(s)
+    if not any(synd):
+        return word >> (BCH_N - BCH_K)
+    # Berlekamp-Massey: shortest LFSR (error locator sigma) generating S_1..S_22
+    sigma, prev = [1], [1]
+    L, m, bprev = 0, 1, 1
+    for n_ in range(2 * BCH_T):
+        disc = synd[n_]
+        for i in range(1, L + 1):
+            if i < len(sigma):
+                disc ^= _gf_mul(sigma[i], synd[n_ - i])
+        if disc == 0:
+            m += 1
+            continue
+        coef = _gf_mul(disc, _GF_EXP[(63 - _GF_LOG[bprev]) % 63])
+        nxt = sigma + [0] * max(0, len(prev) + m - len(sigma))
+        for i, c in enumerate(prev):
+            nxt[i + m] ^= _gf_mul(coef, c)
+        if 2 * L <= n_:
+            prev, L, bprev, m = sigma, n_ + 1 - L, disc, 1
+        else:
+            m += 1
+        sigma = nxt
+    if L > BCH_T:
+        return None
+    # Chien search: error at position p where sigma(alpha^-p) = 0
+    errors = []
+    for p in range(BCH_N):
+        acc = 0
+        for i, c in enumerate(sigma):
+            if c:
+                acc ^= _gf_mul(c, _GF_EXP[(-i * p) % 63])
+        if acc == 0:
+            errors.append(p)
+    if len(errors) != L:
+        return None
+    for p in errors:
+        word ^= 1 << p
+    return word >> (BCH_N - BCH_K)
+
+
+def code_length() -> int:
+    """l: bits of the code of one index."""
+    return BCH_N
+
+
+def code_encode(x: int) -> list[int]:
+    """E(x): the 63 bits (position 0 first) of the codeword of message x + 1."""
+    if not 0 <= x < (1 << BCH_K) - 1:
+        raise ValueError("index out of the code's range")
+    w = bch_encode(x + 1)
+    return [(w >> p) & 1 for p in range(BCH_N)]
+
+
+def code_decode(bits):
+    """x from a (corrupted) 63-bit string, or None if the decoder fails or
+    finds message 0 (no index)."""
+    w = 0
+    for p, v in enumerate(bits):
+        if int(v):
+            w |= 1 << p
+    msg = bch_decode(w)
+    if msg is None or msg == 0:
+        return None
+    return msg - 1
 
 
 def masked_sketches(A: np.ndarray, B: np.ndarray, tables, b: int, subtract_diag: bool = False):
     """Count sketches, with the same hash functions, of the submatrix products
-    of eq. (3): (I_{E_r} A) B for the 2 L1 bits r of the row code and
-    A (B I_{E_r}) for the 2 L3 bits of the column code.  Returns
-    (c_rows (2L1, d, b), c_cols (2L3, d, b))."""
+    of eq. (3): (I_{E_r} A) B for the l bits r of the row code and
+    A (B I_{E_r}) for the l bits of the column code.  Returns
+    (c_rows (l, d, b), c_cols (l, d, b))."""
     A = np.asarray(A, dtype=np.float64); B = np.asarray(B, dtype=np.float64)
     n1, n3 = A.shape[0], B.shape[1]
-    L1, L3 = code_bits(n1), code_bits(n3)
-    E1 = np.array([code_encode(i, L1) for i in range(n1)])   # (n1, 2 L1)
-    E3 = np.array([code_encode(j, L3) for j in range(n3)])   # (n3, 2 L3)
+    ell = code_length()
+    E1 = np.array([code_encode(i) for i in range(n1)])   # (n1, l)
+    E3 = np.array([code_encode(j) for j in range(n3)])   # (n3, l)
     rows, cols = [], []
-    for r in range(2 * L1):
+    for r in range(ell):
         P = (A * E1[:, r][:, None]) @ B
         if subtract_diag:
             np.fill_diagonal(P, 0.0)
         rows.append(bin_product(P, tables, b))
-    for r in range(2 * L3):
+    for r in range(ell):
         P = A @ (B * E3[:, r][None, :])
         if subtract_diag:
             np.fill_diagonal(P, 0.0)
@@ -514,14 +658,16 @@ def find_significant(c_rows: np.ndarray, c_cols: np.ndarray, n1: int, n3: int, d
     into a multiset; positions inserted fewer than d/2 times are deleted.
     Returns the sorted linear indices i*n3 + j of the kept positions and the
     multiset counts."""
-    L1, L3 = code_bits(n1), code_bits(n3)
+    ell = code_length()
     d, b = c_rows.shape[1], c_rows.shape[2]
     counts: dict[int, int] = {}
     for t in range(d):
         for k in range(b):
-            s1 = [abs(c_rows[r, t, k]) > delta / 2 for r in range(2 * L1)]
-            s3 = [abs(c_cols[r, t, k]) > delta / 2 for r in range(2 * L3)]
-            i, j = code_decode(s1, L1), code_decode(s3, L3)
+            s1 = [abs(c_rows[r, t, k]) > delta / 2 for r in range(ell)]
+            s3 = [abs(c_cols[r, t, k]) > delta / 2 for r in range(ell)]
+            if sum(s1) == 0 or sum(s3) == 0:      # message 0: nothing here
+                continue
+            i, j = code_decode(s1), code_decode(s3)
             if i is None or j is None or i >= n1 or j >= n3:
                 continue
             key = i * n3 + j

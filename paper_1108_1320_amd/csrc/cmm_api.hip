@@ -1977,6 +1977,39 @@ int cmm_frobenius_bound(cmm_ctx* ctx, const void* A, int64_t lda, const void* B,
   return CMM_OK;
 }
 
+// The extraction's code (Section 4): the binary BCH code of length 63 with
+// designed distance 23.  Its generator is the product of (x - alpha^j) over
+// the union of the cyclotomic cosets (j, 2j, 4j, ... mod 63) of j = 1 .. 22,
+// computed in GF(2^6) (primitive polynomial x^6 + x + 1); the coefficients
+// of that product lie in GF(2).  Returned as a bit mask (bit i = x^i,
+// degree 47).
+constexpr int kExtractCodeLen = 63;
+
+uint64_t bch_generator() {
+  int ex[63], lg[64];
+  int v = 1;
+  for (int i = 0; i < 63; ++i) {
+    ex[i] = v; lg[v] = i;
+    v <<= 1;
+    if (v & 64) v ^= 0x43;
+  }
+  auto mul = [&](int a, int b) { return (a == 0 || b == 0) ? 0 : ex[(lg[a] + lg[b]) % 63]; };
+  bool root[63] = {};
+  for (int j = 1; j <= 22; ++j)
+    for (int c = j % 63; !root[c]; c = (2 * c) % 63) root[c] = true;
+  int poly[64] = {1};   // GF(64) coefficients, lowest degree first
+  int deg = 0;
+  for (int c = 0; c < 63; ++c) {
+    if (!root[c]) continue;
+    for (int i = deg + 1; i >= 1; --i) poly[i] = poly[i - 1] ^ mul(poly[i], ex[c]);
+    poly[0] = mul(poly[0], ex[c]);
+    ++deg;
+  }
+  uint64_t g = 0;
+  for (int i = 0; i <= deg; ++i) g |= (uint64_t)(poly[i] & 1) << i;
+  return g;
+}
+
 int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B, int64_t ldb,
                          int64_t n1, int64_t m, int64_t n3, int32_t dtype, const float* scaleA,
                          const float* scaleB, int64_t b, int32_t d, uint64_t seed, uint32_t flags,
@@ -1996,8 +2029,7 @@ int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B
     return fail(ctx, CMM_EINVAL, "scales are only taken with CMM_FP8_E4M3");
   CMM_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
-  auto code_bits = [](int64_t n) { int L = 1; while (L < 62 && (int64_t(1) << L) < n) ++L; return L; };
-  const int L1 = code_bits(n1), L3 = code_bits(n3);
+  const int ell = kExtractCodeLen;   // bits of the code of one index (both sides)
   const int64_t db = (int64_t)d * b;
 
   cmm_sketch* sk = new cmm_sketch();
@@ -2013,7 +2045,9 @@ int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B
   uint32_t nfound = 0;
   {
     Work w(ctx);
-    float* cr = w.get<float>((size_t)2 * (L1 + L3) * db);
+    float* cr = w.get<float>((size_t)2 * ell * db);
+    uint64_t* cw1 = w.get<uint64_t>((size_t)n1);
+    uint64_t* cw3 = w.get<uint64_t>((size_t)n3);
     double* ctmp = w.get<double>((size_t)db);
     float* mask = w.get<float>((size_t)std::max(n1, n3));
     double* diagm = (flags & CMM_SUBTRACT_DIAG) ? w.get<double>((size_t)n1) : nullptr;
@@ -2023,14 +2057,18 @@ int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B
     int64_t* outk = w.get<int64_t>((size_t)std::max<int64_t>(cap, 1));
     uint32_t* cnt = w.get<uint32_t>(1);
     uint64_t* pdev = w.get<uint64_t>((size_t)d * 8);
-    if (!cr || !ctmp || !mask || ((flags & CMM_SUBTRACT_DIAG) && !diagm) || !keys || !tkeys || !tcnt ||
-        !outk || !cnt || !pdev) {
+    if (!cr || !cw1 || !cw3 || !ctmp || !mask || ((flags & CMM_SUBTRACT_DIAG) && !diagm) || !keys ||
+        !tkeys || !tcnt || !outk || !cnt || !pdev) {
       release_sketch(sk);
       return fail(ctx, CMM_ENOMEM, "workspace allocation failed");
     }
     rc = CMM_OK;
     if (hipMemcpyAsync(pdev, sk->params.data(), sizeof(uint64_t) * d * 8, hipMemcpyHostToDevice, s) != hipSuccess)
       rc = fail(ctx, CMM_EHIP, "parameter upload failed");
+    const uint64_t gen = bch_generator();
+    if (rc == CMM_OK && (cmm::launch_code_words((int)n1, gen, cw1, s) != hipSuccess ||
+                         cmm::launch_code_words((int)n3, gen, cw3, s) != hipSuccess))
+      rc = fail(ctx, CMM_EHIP, "code word launch failed");
     // the sketch of AB itself, keeping its workspace (layout, both count sketches)
     WsSpec spec;
     WsPtrs ptr;
@@ -2053,11 +2091,11 @@ int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B
       cmm::SideDesc side[2];
       bind_sides(g, sk, op, spec, ptr, side);
       const int64_t nn[2] = {n1, n3};
-      const int Ls[2] = {L1, L3};
+      const uint64_t* cws[2] = {cw1, cw3};
       const float* scl[2] = {scaleA, scaleB};
       // the sketch of the product with side q's index weighted by code bit r
       auto masked = [&](int q, int r, int64_t slot) -> int {
-        CMM_HIP(ctx, cmm::launch_code_mask((int)nn[q], Ls[q], r, scl[q], mask, s));
+        CMM_HIP(ctx, cmm::launch_code_mask((int)nn[q], r, cws[q], scl[q], mask, s));
         side[q].scale = mask;
         CMM_HIP(ctx, cmm::launch_countsketch(dtype, g, side[q], s));
         CMM_HIP(ctx, cmm::launch_fft_mac(g, side[0], side[1], tw32, (float2*)ptr.p[W_PPART], s,
@@ -2065,7 +2103,7 @@ int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B
         CMM_HIP(ctx, cmm::launch_ifft(g, (float2*)ptr.p[W_PPART], (double2*)ptr.p[W_WORK0],
                                       (double2*)ptr.p[W_WORK1], tw64, ctmp, s));
         if (diagm) {
-          CMM_HIP(ctx, cmm::launch_code_mask_diag((int)n1, Ls[q], r, (const double*)ptr.p[W_DIAG], diagm, s));
+          CMM_HIP(ctx, cmm::launch_code_mask_diag((int)n1, r, cws[q], (const double*)ptr.p[W_DIAG], diagm, s));
           CMM_HIP(ctx, cmm::launch_sub_diag(g, sk->hs1, sk->hs2, (int)n1, (int)n3, diagm, (int)n1, ctmp,
                                             ptr.p[W_WORK0], s));
         }
@@ -2074,14 +2112,14 @@ int cmm_find_significant(cmm_ctx* ctx, const void* A, int64_t lda, const void* B
       };
       Scope sc_(ctx, "extract");
       // column-code sketches, then the row-code ones (B's sketch restored)
-      for (int r = 0; r < 2 * L3 && rc == CMM_OK; ++r) rc = masked(1, r, 2 * L1 + r);
+      for (int r = 0; r < ell && rc == CMM_OK; ++r) rc = masked(1, r, ell + r);
       if (rc == CMM_OK) {
         side[1].scale = scaleB;
         if (cmm::launch_countsketch(dtype, g, side[1], s) != hipSuccess) rc = fail(ctx, CMM_EHIP, "countsketch launch failed");
       }
-      for (int r = 0; r < 2 * L1 && rc == CMM_OK; ++r) rc = masked(0, r, r);
+      for (int r = 0; r < ell && rc == CMM_OK; ++r) rc = masked(0, r, r);
       if (rc == CMM_OK) {
-        hipError_t e = cmm::launch_extract_decode(cr, d, b, L1, L3, (int)n1, (int)n3, (float)(0.5 * delta), keys, s);
+        hipError_t e = cmm::launch_extract_decode(cr, d, b, (int)n1, (int)n3, (float)(0.5 * delta), keys, s);
         if (e == hipSuccess) e = cmm::launch_fill_i32((int32_t*)tkeys, 2 * tsize, -1, s);
         if (e == hipSuccess) e = cmm::launch_fill_i32((int32_t*)tcnt, tsize, 0, s);
         if (e == hipSuccess) e = cmm::launch_fill_i32((int32_t*)cnt, 1, 0, s);

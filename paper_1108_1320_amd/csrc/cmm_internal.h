@@ -209,11 +209,16 @@ hipError_t launch_ams_rows(int dtype, const void* X, int64_t ld, const float* sc
 hipError_t launch_ams_final(const double* u, const double* v, int m, int d, const uint64_t* mask1,
                             const uint64_t* mask2, const double* diag, int ndiag, double* X,
                             hipStream_t s);
-hipError_t launch_code_mask(int n, int L, int r, const float* scale, float* out, hipStream_t s);
-hipError_t launch_code_mask_diag(int n, int L, int r, const double* diag, double* out,
+// The extraction's code: codewords of messages x + 1 (x < n) of the
+// length-63 BCH code with generator g (bit mask of degree 47), masks of bit
+// r, and the decode of every (t, k) into a key i * n3 + j or -1.
+hipError_t launch_code_words(int n, uint64_t g, uint64_t* cw, hipStream_t s);
+hipError_t launch_code_mask(int n, int r, const uint64_t* cw, const float* scale, float* out,
+                            hipStream_t s);
+hipError_t launch_code_mask_diag(int n, int r, const uint64_t* cw, const double* diag, double* out,
                                  hipStream_t s);
-hipError_t launch_extract_decode(const float* c, int d, int64_t b, int L1, int L3, int n1, int n3,
-                                 float half_delta, int64_t* keys, hipStream_t s);
+hipError_t launch_extract_decode(const float* c, int d, int64_t b, int n1, int n3, float half_delta,
+                                 int64_t* keys, hipStream_t s);
 hipError_t launch_vote(const int64_t* keys, int64_t nkeys, unsigned long long* tkeys,
                        uint32_t* tcnt, int64_t tsize, int d, int64_t* out, uint32_t* count,
                        int64_t cap, hipStream_t s);

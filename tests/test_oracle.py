@@ -496,19 +496,99 @@ def test_frobenius_bound_holds_and_is_not_vacuous():
 # sublinear extraction (Section 4, Figure 3) with the complement code
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n", [1, 2, 3, 1000, 4096])
-def test_code_roundtrip_and_detection(n):
-    L = O.code_bits(n)
-    assert (1 << L) >= n
-    for x in range(0, n, max(1, n // 300)):
-        e = O.code_encode(x, L)
-        assert len(e) == 2 * L and sum(e) == L
-        assert O.code_decode(e, L) == x
-        for q in range(2 * L):                 # any single flipped bit is detected
-            f = list(e); f[q] ^= 1
-            assert O.code_decode(f, L) is None
-    assert O.code_decode([0] * (2 * L), L) is None   # empty bucket
-    assert O.code_decode([1] * (2 * L), L) is None   # two colliding entries
+def test_bch_generator_known_answer():
+    """The generator polynomial of the binary primitive BCH code of length 63
+    correcting 11 errors, as tabulated in octal in the coding-theory
+    literature (Lin and Costello, Error Control Coding, appendix of BCH
+    generator polynomials: n = 63, k = 16, t = 11): 6331141367235453."""
+    assert O.BCH_G == 0o6331141367235453
+
+
+def test_bch_generator_divides_x63_plus_1_and_has_the_roots():
+    """g(x) divides x^63 + 1 over GF(2) (plain polynomial long division,
+    independent of the field tables), has degree 63 - 16, and vanishes at
+    alpha^1 .. alpha^22 (evaluated by Horner's rule in GF(2^6))."""
+    g = O.BCH_G
+    assert g.bit_length() - 1 == 47
+    a, m = (1 << 63) | 1, g
+    while a and a.bit_length() >= m.bit_length():
+        a ^= m << (a.bit_length() - m.bit_length())
+    assert a == 0
+    # GF(2^6) by shift-and-reduce multiplication (no tables)
+    def mul(x, y):
+        r = 0
+        while y:
+            if y & 1:
+                r ^= x
+            y >>= 1
+            x <<= 1
+            if x & 64:
+                x ^= 0b1000011
+        return r
+    def power(x, e):
+        r = 1
+        for _ in range(e):
+            r = mul(r, x)
+        return r
+    alpha = 2
+    for j in range(1, 23):
+        aj = power(alpha, j)
+        acc = 0
+        for bit in range(g.bit_length() - 1, -1, -1):
+            acc = mul(acc, aj) ^ ((g >> bit) & 1)
+        assert acc == 0, j
+
+
+def test_bch_minimum_distance_by_enumeration():
+    """Every non-zero codeword has weight >= 23 (the code is linear, so the
+    minimum distance is the minimum weight): all 65535 messages."""
+    assert min(bin(O.bch_encode(m)).count("1") for m in range(1, 1 << 16)) >= 23
+    assert O.bch_encode(5) >> 47 == 5                         # systematic
+
+
+def test_bch_decodes_up_to_eleven_errors():
+    """DECODE recovers the index from any string within distance
+    floor(delta l) = 11 of its codeword: random messages with 0..11 random
+    flips, and the worst placements (the 11 highest and the 11 lowest bit
+    positions)."""
+    g = np.random.default_rng(5)
+    for trial in range(400):
+        x = int(g.integers(0, 65534))
+        e = O.code_encode(x)
+        flips = g.choice(63, int(g.integers(0, 12)), replace=False) if trial % 3 else g.choice(63, 11, replace=False)
+        f = list(e)
+        for q in flips:
+            f[q] ^= 1
+        assert O.code_decode(f) == x
+    for x in (0, 1, 4095, 65533):
+        for block in (range(52, 63), range(0, 11)):
+            f = O.code_encode(x)
+            for q in block:
+                f[q] ^= 1
+            assert O.code_decode(f) == x
+
+
+def test_bch_empty_and_beyond_capacity():
+    """A string of weight <= 11 (an empty bucket, or one entry whose bits
+    mostly drowned) is message 0 or nothing, never an index; strings far from
+    every codeword (14 flips) are rejected rather than decoded wrongly in
+    these trials."""
+    assert O.code_decode([0] * 63) is None
+    g = np.random.default_rng(6)
+    for _ in range(100):
+        w = [0] * 63
+        for q in g.choice(63, int(g.integers(1, 12)), replace=False):
+            w[q] = 1
+        assert O.code_decode(w) is None
+    wrong = 0
+    for _ in range(100):
+        x = int(g.integers(0, 65534))
+        f = O.code_encode(x)
+        for q in g.choice(63, 14, replace=False):
+            f[q] ^= 1
+        r = O.code_decode(f)
+        wrong += r is not None and r != x
+    assert wrong == 0
 
 
 def _sparse_product(n1, m, n3, nnz, seed, small=0):
@@ -549,18 +629,20 @@ def test_find_significant_omits_entries_below_delta():
 
 def test_masked_sketch_definition():
     """Masked sketch r is the sketch of the product with the rows (columns)
-    whose code bit r is 0 removed: with every bit pair complementary, the
-    two sketches of a pair add up to the sketch of the whole product."""
+    whose code bit r is 0 removed: it equals the whole product's sketch minus
+    the sketch of the product restricted to the other rows (columns)."""
     g = np.random.default_rng(2)
     A = g.standard_normal((20, 9)); B = g.standard_normal((9, 13))
     tabs = O.hash_tables(O.hash_params(4, 3), 20, 13, 64)
     cr, cc = O.masked_sketches(A, B, tabs, 64)
     whole = O.bin_product(A @ B, tabs, 64)
-    L1, L3 = O.code_bits(20), O.code_bits(13)
-    for q in range(L1):
-        np.testing.assert_allclose(cr[q] + cr[q + L1], whole, atol=1e-12)
-    for q in range(L3):
-        np.testing.assert_allclose(cc[q] + cc[q + L3], whole, atol=1e-12)
+    E1 = np.array([O.code_encode(i) for i in range(20)])
+    E3 = np.array([O.code_encode(j) for j in range(13)])
+    for r in (0, 17, 46, 62):
+        rest = O.bin_product(((1 - E1[:, r])[:, None] * A) @ B, tabs, 64)
+        np.testing.assert_allclose(cr[r] + rest, whole, atol=1e-12)
+        rest = O.bin_product(A @ (B * (1 - E3[:, r])[None, :]), tabs, 64)
+        np.testing.assert_allclose(cc[r] + rest, whole, atol=1e-12)
 
 
 # --------------------------------------------------------------------------
