@@ -603,7 +603,7 @@ def main():
               "ms_per_step_with_kernel_events", "kernel_ms_per_step", "countsketch", "decode_topk_ms"):
         out[k] = head[k]
     if not args.no_stream:
-        sc = stream_ceiling(ctx, gib=0.5, reps=5)
+        sc = stream_ceiling(ctx, gib=1.0, reps=10)
         out["stream_ceiling"] = sc
         best = max(sc["read1_write5"]["GBps"], sc["read1_write5_nt"]["GBps"])
         out["countsketch"]["measured_ceiling_GBps"] = best

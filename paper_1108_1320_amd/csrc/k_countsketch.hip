@@ -119,38 +119,53 @@ __global__ __launch_bounds__(kCsThreads) void k_countsketch(SideDesc sd, int d, 
       const uint32_t* tab = sd.tab + (int64_t)t * sd.Lrow;
       float* out = sd.SA + ((int64_t)t * m + k) * sd.Lrow;
       float amax = 0.0f;
-      for (int idx = tid; idx < total4; idx += kCsThreads) {
-        const int w = idx / L4;
-        const int p = w * sd.Lcap + 4 * (idx - w * L4);
-        const uint4 e4 = *(const uint4*)&tab[p];
-        const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
-        float v[4];
+      // groups of four positions, UQ per thread at a time: their table reads
+      // are issued together, so several are in flight before the gathers
+      // and stores that depend on them
+      constexpr int UQ = 3;
+      for (int base = tid; base < total4; base += UQ * kCsThreads) {
+        uint4 e4s[UQ];
+        int ps[UQ];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t e = ev[q];
-          float x = 0.0f;
-          if (e != CMM_PAD_TAB) {
-            x = val((int)(e & CMM_TAB_IDX));
-            if (e & CMM_TAB_NEG) x = -x;
-            if (e & CMM_TAB_MORE) {
-              const int64_t tp = (int64_t)t * sd.Lrow + p + q;
-              const int c = sd.cntp[tp];
-              const int32_t* mem = sd.perm + (int64_t)t * n + sd.moff[tp];
-              const int32_t* hs = sd.hs + (int64_t)t * n;
-              for (int a = 1; a < c; ++a) {
-                const int xm = mem[a];
-                const float y = val(xm);
-                x += (hs[xm] & 1) ? -y : y;
+        for (int u = 0; u < UQ; ++u) {
+          const int idx = base + u * kCsThreads;
+          const int w = idx / L4;
+          ps[u] = w * sd.Lcap + 4 * (idx - w * L4);
+          if (idx < total4) e4s[u] = *(const uint4*)&tab[ps[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < UQ; ++u) {
+          if (base + u * kCsThreads >= total4) break;
+          const int p = ps[u];
+          const uint32_t ev[4] = {e4s[u].x, e4s[u].y, e4s[u].z, e4s[u].w};
+          float v[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const uint32_t e = ev[q];
+            float x = 0.0f;
+            if (e != CMM_PAD_TAB) {
+              x = val((int)(e & CMM_TAB_IDX));
+              if (e & CMM_TAB_NEG) x = -x;
+              if (e & CMM_TAB_MORE) {
+                const int64_t tp = (int64_t)t * sd.Lrow + p + q;
+                const int c = sd.cntp[tp];
+                const int32_t* mem = sd.perm + (int64_t)t * n + sd.moff[tp];
+                const int32_t* hs = sd.hs + (int64_t)t * n;
+                for (int a = 1; a < c; ++a) {
+                  const int xm = mem[a];
+                  const float y = val(xm);
+                  x += (hs[xm] & 1) ? -y : y;
+                }
               }
             }
+            v[q] = x;
+            amax = fmaxf(amax, fabsf(x));
           }
-          v[q] = x;
-          amax = fmaxf(amax, fabsf(x));
+          // streaming store: the sketches are several times larger than the
+          // caches and are read back only by the spectral kernel
+          typedef float v4f __attribute__((ext_vector_type(4)));
+          __builtin_nontemporal_store(v4f{v[0], v[1], v[2], v[3]}, reinterpret_cast<v4f*>(&out[p]));
         }
-        // streaming store: the sketches are several times larger than the
-        // caches and are read back only by the spectral kernel
-        typedef float v4f __attribute__((ext_vector_type(4)));
-        __builtin_nontemporal_store(v4f{v[0], v[1], v[2], v[3]}, reinterpret_cast<v4f*>(&out[p]));
       }
       for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
       if ((tid & 63) == 0) atomicMax(&smax[par][t], __float_as_uint(amax));   // d <= 63
