@@ -58,6 +58,15 @@ struct FftArgs {
   int R, rows, nrow, roff, d, m, KS, nwg, remap;
 };
 
+// LDS element at byte offset `off` (fold entries and stage writes carry byte
+// offsets).
+template <typename V> __device__ __forceinline__ V& at_byte(V* base, uint32_t off) {
+  return *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + off);
+}
+template <typename V> __device__ __forceinline__ const V& at_byte(const V* base, uint32_t off) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + off);
+}
+
 constexpr int ipow16(int e) { return e <= 0 ? 1 : 16 * ipow16(e - 1); }
 
 template <int L> struct FftShape {
@@ -73,17 +82,37 @@ template <int L> struct FftShape {
   static constexpr int U = L == 12 ? 17 : (L == 13 ? 4 : 8);
   static constexpr int span(int s) { return s == 0 ? 1 : (E ? (1 << E) : 16) * ipow16(s - 1); }
   static constexpr int radix(int s) { return (s == 0 && E) ? (1 << E) : 16; }
-  // twiddle tables of the middle stages 1 .. S-2, one after the other:
-  // stage s starts at tmoff(s) and holds 15 * span(s) entries
+  // At L = 12 the one middle stage takes its 15 twiddles from registers
+  // (like the last stage); other row lengths read those of their middle
+  // stages 1 .. S-2 from an LDS table, stage s from tmoff(s) on, 15 *
+  // span(s) entries (shorter rows run their fold batch and transform in
+  // fewer registers, but 30 more would spill there).
+  static constexpr bool kRegMid = L == 12;
   static constexpr int tmoff(int s) { return s <= 1 ? 0 : tmoff(s - 1) + 15 * span(s - 1); }
-  static constexpr int NMID = S >= 3 ? tmoff(S - 1) : 0;
+  static constexpr int NMID = (S >= 3 && !kRegMid) ? tmoff(S - 1) : 0;
 };
 
+// Byte offset of the write of output r in stages 0 and 1 of a radix-16
+// row: position sw(16 j + r) for stage 0 and sw(256 (j / 16) + (j mod 16) +
+// 16 r) for stage 1.  The swizzle only mixes bits 4..7 into bits 0..3, so
+// both are one base per thread xor a multiple of r: 8 r and 136 r.  The base
+// is made opaque so that it is formed once per stage instead of 16 offsets
+// being held in registers across the loop.
+template <int s> __device__ __forceinline__ int stage_write_base(int j) {
+  int A = s == 0 ? 128 * j + 8 * (j & 15) : 2048 * (j >> 4) + 8 * (j & 15);
+  asm volatile("" : "+v"(A));
+  return A;
+}
+
 template <int L, int s> struct Stage {
-  // tl: last-stage twiddles (registers); tm: middle-stage table in LDS,
-  // tm[(r - 1) * Ns + (j mod Ns)] = omega_{16 Ns}^((j mod Ns) r)
+  // tl: last-stage twiddles and tm1: middle-stage twiddles (registers,
+  // three stages); tm: middle-stage table in LDS (four stages),
+  // tm[(r - 1) * Ns + (j mod Ns)] = omega_{16 Ns}^((j mod Ns) r).  With
+  // kPre every input of stage 0 is first multiplied by pre.
+  template <bool kPre>
   static __device__ __forceinline__ void run(float2* v, float2* P0, float2* P1,
-                                             const float2 (&tl)[15], const float2* tm, int j) {
+                                             const float2 (&tl)[15], const float2 (&tm1)[15],
+                                             const float2* tm, int j, float2 pre) {
     typedef FftShape<L> F;
     constexpr int Rs = F::radix(s);
     constexpr int BPT = 16 / Rs;
@@ -91,38 +120,57 @@ template <int L, int s> struct Stage {
     float2* bin = (s % 2 == 0) ? P0 : P1;
     float2* bout = (s % 2 == 0) ? P1 : P0;
     if constexpr (s > 0) {
+      // radix 16; the twiddles of inputs 1..15 enter the first butterflies
 #pragma unroll
       for (int q = 0; q < 16; ++q) v[q] = bin[own<F::T>(sw(j), j, q)];
       if constexpr (s == F::S - 1) {
-#pragma unroll
-        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tl[r - 1]);
+        dft16_tw(v, tl);
+      } else if constexpr (F::kRegMid) {
+        dft16_tw(v, tm1);
       } else {
+        // table twiddles are multiplied in as they arrive (fewer registers)
         const int jm = j % Ns;
         const float2* tms = tm + F::tmoff(s);
 #pragma unroll
         for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tms[(r - 1) * Ns + jm]);
+        dft16(v);
       }
-    }
+    } else if constexpr (Rs == 16) {
+      if constexpr (kPre) dft16_scaled(v, pre);
+      else dft16(v);
+    } else {
+      if constexpr (kPre) {
 #pragma unroll
-    for (int mi = 0; mi < BPT; ++mi) {
-      float2 x[Rs];
+        for (int q = 0; q < 16; ++q) v[q] = cmul(v[q], pre);
+      }
 #pragma unroll
-      for (int r = 0; r < Rs; ++r) x[r] = v[mi + r * BPT];
-      dft<Rs>(x);
+      for (int mi = 0; mi < BPT; ++mi) {
+        float2 x[Rs];
 #pragma unroll
-      for (int r = 0; r < Rs; ++r) v[mi + r * BPT] = x[r];
+        for (int r = 0; r < Rs; ++r) x[r] = v[mi + r * BPT];
+        dft<Rs>(x);
+#pragma unroll
+        for (int r = 0; r < Rs; ++r) v[mi + r * BPT] = x[r];
+      }
     }
     if constexpr (s < F::S - 1) {
       if constexpr (s == 0 && F::S % 2 == 0) __syncthreads();
+      if constexpr (Rs == 16 && (s == 0 || Ns == 16)) {
+        const int A = stage_write_base<s>(j);
+        constexpr int K = s == 0 ? 8 : 136;
 #pragma unroll
-      for (int mi = 0; mi < BPT; ++mi) {
-        const int jb = j + F::T * mi;
-        const int base = (jb / Ns) * Ns * Rs + (jb % Ns);
+        for (int r = 0; r < 16; ++r) at_byte(bout, (uint32_t)(A ^ (K * r))) = v[r];
+      } else {
 #pragma unroll
-        for (int r = 0; r < Rs; ++r) bout[sw(base + r * Ns)] = v[mi + r * BPT];
+        for (int mi = 0; mi < BPT; ++mi) {
+          const int jb = j + F::T * mi;
+          const int base = (jb / Ns) * Ns * Rs + (jb % Ns);
+#pragma unroll
+          for (int r = 0; r < Rs; ++r) bout[sw(base + r * Ns)] = v[mi + r * BPT];
+        }
       }
       __syncthreads();
-      Stage<L, s + 1>::run(v, P0, P1, tl, tm, j);
+      Stage<L, s + 1>::template run<false>(v, P0, P1, tl, tm1, tm, j, pre);
     }
   }
 };
@@ -183,13 +231,6 @@ __device__ __forceinline__ int2 unpack2(unsigned long long p) {
   return make_int2((int)lo, (int)(hi + (lo >> 31)));
 }
 
-// LDS element at byte offset `off` (fold entries carry byte offsets).
-template <typename V> __device__ __forceinline__ V& at_byte(V* base, uint32_t off) {
-  return *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + off);
-}
-template <typename V> __device__ __forceinline__ const V& at_byte(const V* base, uint32_t off) {
-  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + off);
-}
 
 // omega_32^q = exp(-2 pi i q / 32) for q < 16 (cos, sin of q pi / 16)
 constexpr float kW32[16][2] = {
@@ -342,8 +383,16 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
     for (int r = 1; r < 16; ++r)
       tl[r - 1] = a.tw[(int64_t)((j % Ns) * r) * (C / (16 * Ns)) * R];
   }
+  // middle-stage twiddles omega_{16 Ns}^((j mod Ns) r), Ns = span(1):
+  // registers with three stages, the LDS table with four
+  float2 tm1[15];
+  if constexpr (F::kRegMid) {
+    constexpr int Ns = F::span(1);
 #pragma unroll
-  for (int s = 1; s < F::S - 1; ++s) {
+    for (int r = 1; r < 16; ++r) tm1[r - 1] = a.tw[(int64_t)((j % Ns) * r) * (C / (16 * Ns)) * R];
+  }
+#pragma unroll
+  for (int s = 1; s < F::S - 1 && !F::kRegMid; ++s) {
     const int Ns = F::span(s);
     for (int e = j; e < 15 * Ns; e += T) {
       const int r = e / Ns + 1, jm = e % Ns;
@@ -399,7 +448,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
         const int2 zi = unpack2(Z[own<T>(jbase, j, q)]);
         v[q] = make_float2((float)zi.x * inv, (float)zi.y * inv);
       }
-      Stage<L, 0>::run(v, P0, P1, tl, tm, j);
+      Stage<L, 0>::template run<false>(v, P0, P1, tl, tm1, tm, j, make_float2(0.f, 0.f));
       // No thread touches this thread's own positions after the last
       // stage's barrier: clear the Z slots for the next fold and pass the
       // spectrum through P1 to the threads holding the mirror frequencies.
@@ -505,8 +554,16 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
     for (int r = 1; r < 16; ++r)
       tl[r - 1] = a.tw[(int64_t)((j % Ns) * r) * (C / (16 * Ns)) * R];
   }
+  // middle-stage twiddles omega_{16 Ns}^((j mod Ns) r), Ns = span(1):
+  // registers with three stages, the LDS table with four
+  float2 tm1[15];
+  if constexpr (F::kRegMid) {
+    constexpr int Ns = F::span(1);
 #pragma unroll
-  for (int s = 1; s < F::S - 1; ++s) {
+    for (int r = 1; r < 16; ++r) tm1[r - 1] = a.tw[(int64_t)((j % Ns) * r) * (C / (16 * Ns)) * R];
+  }
+#pragma unroll
+  for (int s = 1; s < F::S - 1 && !F::kRegMid; ++s) {
     const int Ns = F::span(s);
     for (int e = j; e < 15 * Ns; e += T) {
       const int r = e / Ns + 1, jm = e % Ns;
@@ -556,21 +613,23 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
       else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0, own_off);
       __builtin_amdgcn_wave_barrier();
+      // the slot factor omega_b^(f1 j) (1 in row 0) and the fixed-point unit
+      // multiply every input of stage 0
+      const float2 pre = f1 != 0 ? make_float2(sj.x * inv, sj.y * inv) : make_float2(inv, 0.0f);
       if (f1 != 0) {
-        const float2 sjs = make_float2(sj.x * inv, sj.y * inv);
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
           const int2 zi = unpack2(Z[own<T>(jbase, j, q)]);
-          v[q] = cmul(make_float2((float)zi.x, (float)zi.y), sjs);
+          v[q] = make_float2((float)zi.x, (float)zi.y);
         }
       } else {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
           const int re = (int)(uint32_t)(Z[own<T>(jbase, j, q)] & 0xFFFFFFFFull);
-          v[q] = make_float2((float)re * inv, 0.0f);
+          v[q] = make_float2((float)re, 0.0f);
         }
       }
-      Stage<L, 0>::run(v, P0, P1, tl, tm, j);
+      Stage<L, 0>::template run<true>(v, P0, P1, tl, tm1, tm, j, pre);
       if (side == 0) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) X[q] = v[q];
