@@ -444,8 +444,10 @@ def run_extract(ctx, w, median_x2):
 def traffic_record(w, geometry):
     """HBM bytes per spectral step (both fft_mac kernels) from the committed
     rocprofv3 counter summary (profiles/fft_mac_traffic.json), if it holds a
-    record of this workload at this geometry (log2c, kmax, cs_blocks) and the
-    kernel source has not changed since the counters were taken (else None)."""
+    record of this workload at this row length and k per block (the first two
+    of log2c, kmax, cs_blocks; the count-sketch blocks do not change the
+    spectral launches) and the kernel source has not changed since the
+    counters were taken (else None)."""
     import hashlib
     rec_path = os.path.join(ROOT, "profiles", "fft_mac_traffic.json")
     src = os.path.join(ROOT, "paper_1108_1320_amd", "csrc", "k_fft_mac.hip")
@@ -456,7 +458,7 @@ def traffic_record(w, geometry):
     if rec.get("fft_mac_source_sha256_16") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
         return None
     for r in rec.get("records", []):
-        if r["workload"] == w.name and list(r["geometry"]) == list(geometry):
+        if r["workload"] == w.name and list(r["geometry"])[:2] == list(geometry)[:2]:
             return r["read_bytes"] + r["write_bytes"]
     return None
 
