@@ -1215,6 +1215,8 @@ int topk_many(cmm_ctx* c, int mode, const std::vector<TopkJob>& jobs) {
     int64_t* oi = nullptr;
     int64_t* oj = nullptr;
     float* ov = nullptr;
+    int log2w = 0;                 // screening bitmap width (0: none)
+    uint32_t* bits = nullptr;
     std::vector<uint32_t> h;
   };
   std::vector<State> st(n);
@@ -1230,7 +1232,9 @@ int topk_many(cmm_ctx* c, int mode, const std::vector<TopkJob>& jobs) {
     x.oi = w.get<int64_t>(jb.K);
     x.oj = w.get<int64_t>(jb.K);
     x.ov = w.get<float>(jb.K);
-    if (!x.hist || !x.count || !x.wide || !x.cand || !x.oi || !x.oj || !x.ov)
+    x.log2w = cmm::screen_log2w(x.dd.d, x.dd.b);
+    if (x.log2w > 0) x.bits = w.get<uint32_t>((size_t)cmm::screen_nf(x.dd.d) << (x.log2w - 5));
+    if (!x.hist || !x.count || !x.wide || !x.cand || !x.oi || !x.oj || !x.ov || (x.log2w > 0 && !x.bits))
       return fail(c, CMM_ENOMEM, "workspace allocation failed");
     x.h.assign(4096, 0u);
   }
@@ -1267,7 +1271,9 @@ int topk_many(cmm_ctx* c, int mode, const std::vector<TopkJob>& jobs) {
       const uint32_t T0 = (uint32_t)x.b0 << 19;
       CMM_HIP(c, cmm::launch_fill_i32((int32_t*)x.hist, 4096, 0, s));
       CMM_HIP(c, cmm::launch_fill_i32((int32_t*)x.count, 2, 0, s));
-      CMM_HIP(c, cmm::launch_topk_hist(x.dd, mode, 1, 0, 32, 19, 0xFFF, x.hist, T0, x.wide, x.count, kWide, s));
+      if (x.log2w > 0) CMM_HIP(c, cmm::launch_screen_bits(x.dd, T0, x.log2w, x.bits, s));
+      CMM_HIP(c, cmm::launch_topk_hist(x.dd, mode, 1, 0, 32, 19, 0xFFF, x.hist, T0, x.wide, x.count, kWide, s,
+                                       x.bits, x.log2w));
       dl.push_back({x.h.data(), x.hist, 4096 * sizeof(uint32_t)});
     }
     if (!dl.empty()) { const int rc_ = download_n(c, s, dl.data(), dl.size()); if (rc_) return rc_; }

@@ -250,10 +250,18 @@ struct TopkCand {
 
 hipError_t launch_estimate(const DecodeDesc& dd, const int64_t* qi, const int64_t* qj, int64_t q,
                            float* out, hipStream_t s);
+// screen: optional bitmap of launch_screen_bits at the same threshold (only
+// read when cand is given, i.e. in the collecting pass).
 hipError_t launch_topk_hist(const DecodeDesc& dd, int mode, int tile_stride, uint32_t prefix,
                             int prefix_shift, int digit_shift, uint32_t digit_mask, uint32_t* hist,
                             uint32_t thresh, TopkCand* cand, uint32_t* count, int cap,
-                            hipStream_t s);
+                            hipStream_t s, const uint32_t* screen = nullptr, int screen_log2w = 0);
+// Rows of the screening bitmap (d - ceil(d/2) + 1), its log2 width per row
+// for (d, b) (0: no screen), and the kernel that builds it for a threshold.
+int screen_nf(int d);
+int screen_log2w(int d, int64_t b);
+hipError_t launch_screen_bits(const DecodeDesc& dd, uint32_t thresh, int log2w, uint32_t* bits,
+                              hipStream_t s);
 hipError_t launch_topk_filter(const TopkCand* in, const uint32_t* in_count, int in_cap,
                               uint32_t thresh, TopkCand* out, uint32_t* out_count, int out_cap,
                               hipStream_t s);

@@ -123,6 +123,33 @@ __device__ __forceinline__ bool in_domain(int mode, int i, int j, int n1, int n3
   return i < n1 && j < n3 && (mode != 1 || i < j);
 }
 
+// Screening bitmap for a key threshold (Section 3.3: |median| >= T needs
+// ceil(d/2) of the d values to reach T in magnitude).  Bit (u mod W) of row t
+// is set when some bucket u' = u (mod W) of repetition t has |c_t[u']| >= T;
+// rows t < nf, W = 2^log2w (a power of two dividing b, at least 64).  A
+// candidate whose first nf = d - ceil(d/2) + 1 buckets all have clear bits
+// cannot reach T (at most d - nf values could), so the pass skips it without
+// touching c; folding several buckets into one bit only lets more candidates
+// through to the exact test.
+__global__ void k_screen_bits(DecodeDesc dd, int nf, int log2w, uint32_t thresh,
+                              uint32_t* __restrict__ bits) {
+  const int64_t W = (int64_t)1 << log2w;
+  const int64_t total = (int64_t)nf * W;   // a multiple of 64
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int t = (int)(idx >> log2w);
+    const int64_t u0 = idx & (W - 1);
+    bool big = false;
+    for (int64_t u = u0; u < dd.b; u += W)
+      big |= (__float_as_uint(dd.c32[(int64_t)t * dd.b + u]) & 0x7FFFFFFFu) >= thresh;
+    const unsigned long long m = __ballot(big);
+    if ((threadIdx.x & 63) == 0) {
+      bits[idx >> 5] = (uint32_t)m;
+      bits[(idx >> 5) + 1] = (uint32_t)(m >> 32);
+    }
+  }
+}
+
 // Histogram of one key digit over the candidates whose key matches
 // `prefix` under `pmask`, over every tile_stride-th tile of 16 rows (1 = the
 // whole domain).  With COLLECT, only candidates with key >= thresh are
@@ -133,13 +160,22 @@ __global__ __launch_bounds__(256) void k_topk_hist(DecodeDesc dd, int mode, int 
                                                    uint32_t pmask, uint32_t prefix, int dshift,
                                                    uint32_t dmask, uint32_t* __restrict__ hist,
                                                    uint32_t thresh, TopkCand* __restrict__ cand,
-                                                   uint32_t* __restrict__ count, int cap) {
+                                                   uint32_t* __restrict__ count, int cap,
+                                                   const uint32_t* __restrict__ screen, int log2w) {
   __shared__ uint32_t h[4096];
+  extern __shared__ uint32_t sbits[];   // the screening bitmap (COLLECT with a screen)
+  constexpr int kNeed = (D + 1) / 2;
+  constexpr int kNF = D - kNeed + 1;
   const int tid = threadIdx.x;
   const int j = blockIdx.x * 256 + tid;
   const int i0 = blockIdx.y * tile_stride * kTI;
   if (mode == 1 && i0 >= (int)(blockIdx.x * 256 + 255)) return;   // tile below the diagonal
   for (int q = tid; q < 4096; q += 256) h[q] = 0;
+  const bool scr = COLLECT && D > 0 && screen != nullptr;
+  const uint32_t wmask = ((uint32_t)1 << log2w) - 1u;
+  const int wrow = scr ? (1 << log2w) >> 5 : 0;   // words per repetition
+  if (scr)
+    for (int q = tid; q < kNF * wrow; q += 256) sbits[q] = screen[q];
   __syncthreads();
   if (j < dd.n3) {
     HashVec<D> h2;
@@ -151,6 +187,15 @@ __global__ __launch_bounds__(256) void k_topk_hist(DecodeDesc dd, int mode, int 
       load_hash<D>(h1, dd.hs1, dd.n1, i, dd.d);
       float est;
       if constexpr (COLLECT && D > 0) {
+        if (scr) {
+          int big = 0;
+#pragma unroll
+          for (int t = 0; t < kNF; ++t) {
+            const uint32_t u = (uint32_t)((h1.v[t] >> 1) + (h2.v[t] >> 1)) & wmask;
+            big += (sbits[t * wrow + (u >> 5)] >> (u & 31)) & 1u;
+          }
+          if (big + (D - kNF) < kNeed) continue;   // cannot reach the threshold
+        }
         est = estimate_above<D>(dd, h1.v, h2.v, __uint_as_float(thresh));
         if (est != est) continue;   // cannot reach the threshold
       } else {
@@ -427,19 +472,38 @@ hipError_t launch_estimate(const DecodeDesc& dd, const int64_t* qi, const int64_
 hipError_t launch_topk_hist(const DecodeDesc& dd, int mode, int tile_stride, uint32_t prefix,
                             int prefix_shift, int digit_shift, uint32_t digit_mask, uint32_t* hist,
                             uint32_t thresh, TopkCand* cand, uint32_t* count, int cap,
-                            hipStream_t s) {
+                            hipStream_t s, const uint32_t* screen, int screen_log2w) {
   const uint32_t pmask = prefix_shift >= 32 ? 0u : ~((1u << prefix_shift) - 1u);
   const int tiles = (dd.n1 + kTI - 1) / kTI;
   dim3 grid((dd.n3 + 255) / 256, (tiles + tile_stride - 1) / tile_stride);
   if (cand) {
-#define CMM_H(DV) hipLaunchKernelGGL((k_topk_hist<DV, true>), grid, dim3(256), 0, s, dd, mode, tile_stride, pmask, prefix & pmask, digit_shift, digit_mask, hist, thresh, cand, count, cap)
+    const size_t slds = screen ? (size_t)screen_nf(dd.d) * ((size_t)1 << screen_log2w) / 8 : 0;
+#define CMM_H(DV) hipLaunchKernelGGL((k_topk_hist<DV, true>), grid, dim3(256), slds, s, dd, mode, tile_stride, pmask, prefix & pmask, digit_shift, digit_mask, hist, thresh, cand, count, cap, screen, screen_log2w)
     CMM_DISPATCH_D(dd.d, CMM_H)
 #undef CMM_H
   } else {
-#define CMM_H(DV) hipLaunchKernelGGL((k_topk_hist<DV, false>), grid, dim3(256), 0, s, dd, mode, tile_stride, pmask, prefix & pmask, digit_shift, digit_mask, hist, 0u, (TopkCand*)nullptr, (uint32_t*)nullptr, 0)
+#define CMM_H(DV) hipLaunchKernelGGL((k_topk_hist<DV, false>), grid, dim3(256), 0, s, dd, mode, tile_stride, pmask, prefix & pmask, digit_shift, digit_mask, hist, 0u, (TopkCand*)nullptr, (uint32_t*)nullptr, 0, (const uint32_t*)nullptr, 0)
     CMM_DISPATCH_D(dd.d, CMM_H)
 #undef CMM_H
   }
+  return hipGetLastError();
+}
+
+int screen_nf(int d) { return d - (d + 1) / 2 + 1; }
+
+int screen_log2w(int d, int64_t b) {
+  // the bitmap of screen_nf(d) rows stays within 32 KB of LDS
+  if (d < 1 || d > 15 || b < 4096) return 0;
+  int lw = 0;
+  while (((int64_t)1 << (lw + 1)) <= b && ((int64_t)screen_nf(d) << (lw + 1)) <= 8 * 32768) ++lw;
+  return lw >= 6 ? lw : 0;
+}
+
+hipError_t launch_screen_bits(const DecodeDesc& dd, uint32_t thresh, int log2w, uint32_t* bits,
+                              hipStream_t s) {
+  const int64_t total = (int64_t)screen_nf(dd.d) << log2w;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_screen_bits, dim3(grid), dim3(256), 0, s, dd, screen_nf(dd.d), log2w, thresh, bits);
   return hipGetLastError();
 }
 
