@@ -272,6 +272,8 @@ TOPK_LARGE = [
     (1600, 1600, 150, 1 << 14, 3, 2048, "upper"),
     (1200, 1300, 100, 1024, 1, 50, "all"),      # d = 1: ~1500 equal magnitudes per bucket
     (1024, 1024, 64, 4096, 1, 1, "upper"),
+    # even d, and b above the screening bitmap's width (several buckets per bit)
+    (1100, 1050, 64, 1 << 17, 6, 100, "all"),
 ]
 
 
