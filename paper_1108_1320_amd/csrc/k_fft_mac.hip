@@ -105,8 +105,8 @@ template <int s> __device__ __forceinline__ int stage_write_base(int j) {
 }
 
 template <int L, int s> struct Stage {
-  // tl: last-stage twiddles and tm1: middle-stage twiddles (registers,
-  // three stages); tm: middle-stage table in LDS (four stages),
+  // tl: last-stage twiddles and tm1: middle-stage twiddles (registers; tm1
+  // at L = 12 only); tm: middle-stage table in LDS (other row lengths),
   // tm[(r - 1) * Ns + (j mod Ns)] = omega_{16 Ns}^((j mod Ns) r).  With
   // kPre every input of stage 0 is first multiplied by pre.
   template <bool kPre>
@@ -230,7 +230,6 @@ __device__ __forceinline__ int2 unpack2(unsigned long long p) {
   const uint32_t lo = (uint32_t)p, hi = (uint32_t)(p >> 32);
   return make_int2((int)lo, (int)(hi + (lo >> 31)));
 }
-
 
 // omega_32^q = exp(-2 pi i q / 32) for q < 16 (cos, sin of q pi / 16)
 constexpr float kW32[16][2] = {
@@ -384,7 +383,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
       tl[r - 1] = a.tw[(int64_t)((j % Ns) * r) * (C / (16 * Ns)) * R];
   }
   // middle-stage twiddles omega_{16 Ns}^((j mod Ns) r), Ns = span(1):
-  // registers with three stages, the LDS table with four
+  // registers at L = 12, the LDS table for the other row lengths
   float2 tm1[15];
   if constexpr (F::kRegMid) {
     constexpr int Ns = F::span(1);
@@ -555,7 +554,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
       tl[r - 1] = a.tw[(int64_t)((j % Ns) * r) * (C / (16 * Ns)) * R];
   }
   // middle-stage twiddles omega_{16 Ns}^((j mod Ns) r), Ns = span(1):
-  // registers with three stages, the LDS table with four
+  // registers at L = 12, the LDS table for the other row lengths
   float2 tm1[15];
   if constexpr (F::kRegMid) {
     constexpr int Ns = F::span(1);
