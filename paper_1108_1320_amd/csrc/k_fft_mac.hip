@@ -326,7 +326,11 @@ __device__ __forceinline__ void fetch_group(Batch<kU>& bt, int g0, const float* 
 }
 
 // The whole segment, batch by batch; batch `a` (kU entries per lane) was
-// fetched during the previous transform.  While a batch is folded, each
+// fetched during the previous transform.  Callers raise the wave's priority
+// for the fold and the next fetch: two waves share a SIMD, and a fold
+// (latency-bound: weight reads, LDS atomics, global loads) then issues ahead
+// of the other wave's transform (issue-bound) and overlaps with it, instead
+// of waiting behind it.  While a batch is folded, each
 // group's registers are refilled with the same group of the next batch
 // right after the group is folded, so the next batch's loads are in flight
 // behind the rest of the folding, with no second buffer.
@@ -437,9 +441,11 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
       (void)frexpf(bound, &ex);
       const float scale = bound > 0.0f ? ldexpf(1.0f, 30 - ex) : 0.0f;
       const float inv = bound > 0.0f ? ldexpf(1.0f, ex - 30) : 0.0f;
+      __builtin_amdgcn_s_setprio(1);
       fold_all<G, kU, kFoldPair, C / 2>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
       else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0, own_off);
+      __builtin_amdgcn_s_setprio(0);
       __syncthreads();   // every wave's adds are in
       float2 v[16];
 #pragma unroll
@@ -606,11 +612,14 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) Z[own<T>(jbase, j, q)] = 0ull;
       __builtin_amdgcn_wave_barrier();
+      // the fold and the fetch run at raised wave priority (see fold_all)
+      __builtin_amdgcn_s_setprio(1);
       if (f1 == 0) fold_all<G, kU, kFoldRow0, C / 2>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
       else fold_all<G, kU, kFoldRow, C / 2>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
       // first batch of the next (side, k), in flight during the transform
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
       else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0, own_off);
+      __builtin_amdgcn_s_setprio(0);
       __builtin_amdgcn_wave_barrier();
       // the slot factor omega_b^(f1 j) (1 in row 0) and the fixed-point unit
       // multiply every input of stage 0
