@@ -24,6 +24,8 @@ The default run also measures the other single-product workloads
 covariance 16384 fp8 with top-256), each with its own tuning, step time,
 per-kernel times, spectral roofline and count-sketch HBM rate, and compares
 the count sketch with plain HBM streams of its shape (``stream_ceiling``).
+``countsketch_d1`` is the count sketch of the default workload's operands with
+one repetition instead of five (the same input read, a fifth of the writes).
 Step times come from a region with the library's timing events off; a second
 region of the same steps with the events on gives the per-kernel times.
 
@@ -37,6 +39,7 @@ call whose host waits all products share.
 from __future__ import annotations
 
 import argparse
+import copy
 import json
 import math
 import os
@@ -604,12 +607,29 @@ def main():
     for k in ("autotune", "hbm_frac", "input_elements_per_s", "nominal_fft_gflops",
               "ms_per_step_with_kernel_events", "kernel_ms_per_step", "countsketch", "decode_topk_ms"):
         out[k] = head[k]
+    if args.workload == 2 and args.d is None and not args.no_configs:
+        # the count sketch of the same operands with one repetition: the
+        # kernel streams its input once whatever d is, so the bytes it writes
+        # (and its HBM rate) fall with d
+        w1 = copy.copy(w)
+        w1.d = 1
+        r1, rk1 = measure(ctx, w1, args.steps, args.warmup, autotune=False, geometry=head["geometry"])
+        rk1["sketch"].free()
+        out["countsketch_d1"] = {"d": 1, "geometry": r1["geometry"], "ms_per_step": r1["ms_per_step"],
+                                 **r1["countsketch"]}
+        del rk1
     if not args.no_stream:
         sc = stream_ceiling(ctx, gib=1.0, reps=10)
         out["stream_ceiling"] = sc
         best = max(sc["read1_write5"]["GBps"], sc["read1_write5_nt"]["GBps"])
         out["countsketch"]["measured_ceiling_GBps"] = best
         out["countsketch"]["frac_of_measured_ceiling"] = round(out["countsketch"]["achieved"] / best, 4)
+        if "countsketch_d1" in out:
+            # one repetition reads about as many bytes as it writes: a copy
+            best1 = max(sc["copy"]["GBps"], sc["copy_nt"]["GBps"])
+            out["countsketch_d1"]["measured_ceiling_GBps"] = best1
+            out["countsketch_d1"]["measured_ceiling_stream"] = "copy"
+            out["countsketch_d1"]["frac_of_measured_ceiling"] = round(out["countsketch_d1"]["achieved"] / best1, 4)
     out["frobenius_bound"] = run_frobenius(ctx, w, args.steps)
     if not args.no_sparse and args.workload == 2:
         out["sparse_form"] = run_sparse(ctx, w, args.steps)
