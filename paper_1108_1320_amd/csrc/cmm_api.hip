@@ -336,11 +336,13 @@ int layout_cap(int64_t n, int64_t b, int W, bool safe) {
 
 // Element counts of every workspace buffer of one product.
 enum WsBuf { W_CNT0, W_POS0, W_ENT0, W_TAB0, W_CNTP0, W_MOFF0, W_FILL0, W_PERM0, W_SEG0, W_LSEG0,
-             W_SA0, W_CMAX0, W_CNT1, W_POS1, W_ENT1, W_TAB1, W_CNTP1, W_MOFF1, W_FILL1, W_PERM1,
-             W_SEG1, W_LSEG1, W_SA1, W_CMAX1, W_PPART, W_WORK0, W_WORK1, W_OFLOW, W_PARTIAL,
+             W_SA0, W_CMAX0, W_ENTP0, W_CNT1, W_POS1, W_ENT1, W_TAB1, W_CNTP1, W_MOFF1, W_FILL1, W_PERM1,
+             W_SEG1, W_LSEG1, W_SA1, W_CMAX1, W_ENTP1, W_PPART, W_WORK0, W_WORK1, W_OFLOW, W_PARTIAL,
              W_DIAG, W_COUNT };
-constexpr size_t kElemSize[W_COUNT] = {4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4,
-                                       4, 4, 4, 4, 8, 16, 16, 4, 8, 8};
+constexpr size_t kElemSize[W_COUNT] = {4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4, 2, 4, 4, 4, 4, 4, 4, 4,
+                                       4, 4, 4, 4, 4, 2, 8, 16, 16, 4, 8, 8};
+static_assert(kElemSize[W_COUNT - 1] != 0 && W_CNT1 - W_CNT0 == W_PPART - W_CNT1,
+              "one element size per workspace buffer, the same buffers for both sides");
 
 struct WsSpec {
   size_t count[W_COUNT] = {};
@@ -358,6 +360,7 @@ WsSpec ws_spec(const cmm::Geometry& g, int64_t n1, int64_t n3, bool safe, uint32
     w.count[W_CNT0 + o] = (size_t)g.d * g.b;
     w.count[W_POS0 + o] = (size_t)g.d * g.b;
     w.count[W_ENT0 + o] = w.count[W_TAB0 + o] = w.count[W_CNTP0 + o] = (size_t)g.d * Lrow;
+    w.count[W_ENTP0 + o] = (size_t)g.d * Lrow;
     w.count[W_MOFF0 + o] = w.count[W_FILL0 + o] = (size_t)g.d * Lrow;
     w.count[W_PERM0 + o] = (size_t)g.d * nn[q];
     w.count[W_SEG0 + o] = (size_t)g.d * g.W;
@@ -453,6 +456,7 @@ void bind_sides(const cmm::Geometry& g, const cmm_sketch* sk, const Operands& op
     sd.cnt = (int32_t*)ptr.p[W_CNT0 + o];
     sd.pos = (int32_t*)ptr.p[W_POS0 + o];
     sd.ent = (uint32_t*)ptr.p[W_ENT0 + o];
+    sd.entp = (uint16_t*)ptr.p[W_ENTP0 + o];
     sd.tab = (uint32_t*)ptr.p[W_TAB0 + o];
     sd.cntp = (int32_t*)ptr.p[W_CNTP0 + o];
     sd.moff = (int32_t*)ptr.p[W_MOFF0 + o];

@@ -99,6 +99,16 @@ __host__ __device__ __forceinline__ uint32_t pad_entry(int w, int G, int r) {
   return (uint32_t)fft_swizzle(w * G + r % G) << 3;
 }
 
+// Fold entry of bucket u for the row pair {0, R/2} (C = 2^log2c): the LDS
+// byte offset of its slot s = (u mod 2C) div 2 (swizzled), with the parity
+// of u in bit 0 (0: the real part of the slot, 1: the imaginary part).  The
+// offset is a multiple of 8 below 8C <= 2^16, so the entry fits 16 bits.
+// Padding positions use pad_entry's value (parity 0, value 0).
+__host__ __device__ __forceinline__ uint16_t pair_entry(uint32_t u, int log2c) {
+  const uint32_t s = (u & ((2u << log2c) - 1u)) >> 1;
+  return (uint16_t)(((uint32_t)fft_swizzle((int)s) << 3) | (u & 1u));
+}
+
 constexpr int kMaxLog2C = 13;          // FFT row length C <= 8192
 // Hashed dimensions n1, n3: rows up to kMaxStagedDim floats are staged in LDS
 // by the count-sketch kernel (sparse operands always are); dense rows up to
@@ -126,7 +136,8 @@ struct SideDesc {
   int32_t* hs;          // [d][n]
   int32_t* cnt;         // [d][b]
   int32_t* pos;         // [d][b]
-  uint32_t* ent;        // [d][Lrow]
+  uint32_t* ent;        // [d][Lrow] fold entries of the rows (fold_entry)
+  uint16_t* entp;       // [d][Lrow] fold entries of the row pair (pair_entry)
   uint32_t* tab;        // [d][Lrow]
   int32_t* cntp;        // [d][Lrow]
   int32_t* moff;        // [d][Lrow]

@@ -49,6 +49,7 @@ template <int T> __device__ __forceinline__ int own(int jbase, int j, int q) {
 struct FftArgs {
   const float* SA0; const float* SA1;
   const uint32_t* ent0; const uint32_t* ent1;
+  const uint16_t* entp0; const uint16_t* entp1;   // the row pair's entries
   const int32_t* lseg0; const int32_t* lseg1;
   const float* cmax0; const float* cmax1;
   int Lcap0, Lcap1, Lrow0, Lrow1;
@@ -186,8 +187,8 @@ template <int U> struct Batch {
 // Past the segment's end a lane gets value 0 and its own first slot.  A
 // batch wholly inside the segment (a wave-uniform test) is loaded without
 // per-entry tests.
-template <int G, int kU>
-__device__ __forceinline__ void fetch(Batch<kU>& bt, const float* sa, const uint32_t* en, int ls,
+template <int G, int kU, typename E>
+__device__ __forceinline__ void fetch(Batch<kU>& bt, const float* sa, const E* en, int ls,
                                       int lane, int first, uint32_t own_off) {
   if ((first + kU) * G <= ls) {
 #pragma unroll
@@ -256,15 +257,17 @@ enum { kFoldRow0 = 0, kFoldRow = 1, kFoldPair = 2 };
 //   P[C]     = Re Z[0] - Im Z[0],
 // and P[2C - f] = conj P[f].  Bucket u folds with weight 1 into slot
 // s = (u mod 2C) div 2, real part for even u mod 2C and imaginary part for
-// odd.  Slot s belongs to thread s mod T, in general not in the wave of
-// the entry, so this fold is bracketed by block barriers.
+// odd.  The layout stores, for each bucket, that slot's LDS offset and the
+// parity of u (pair_entry), so the pair fold reads its target directly.
+// Slot s belongs to thread s mod T, in general not in the wave of the
+// entry, so this fold is bracketed by block barriers.
 
 // The batch is folded in groups of 4 entries (the last group may be
 // shorter): a group that lies wholly past the segment is skipped by a
 // wave-uniform test; inside a group there is no branch, so the weight reads
 // issue together.  Padding entries carry value 0 and an own slot of the
-// wave.  CH = C / 2 (used by the pair mode).
-template <int kU, int MODE, int CH>
+// wave.
+template <int kU, int MODE>
 __device__ __forceinline__ void fold_group(const Batch<kU>& bt, int g0, unsigned long long* Z,
                                            const float2* wf, float scale) {
   constexpr int kG = 4;
@@ -288,31 +291,28 @@ __device__ __forceinline__ void fold_group(const Batch<kU>& bt, int g0, unsigned
     } else if constexpr (MODE == kFoldRow) {
       atomicAdd(&at_byte(Z, off), pack2((int)(sv * w[i].x), (int)(sv * w[i].y)));
     } else {
-      // u mod C from the swizzled slot, the parity of u div C from bit 4 of
-      // the weight index; u mod 2C = (u mod C) + C * parity
-      const int rc = fft_swizzle((int)(off >> 3));
-      const int sl = (rc >> 1) + CH * (int)((e >> 23) & 1u);
+      // pair entry: the slot's byte offset, the real/imaginary choice in bit 0
       const unsigned long long add = (unsigned long long)(long long)(int)sv;
-      atomicAdd(&Z[fft_swizzle(sl)], (rc & 1) ? add << 32 : add);
+      atomicAdd(&at_byte(Z, e & ~7u), add << ((e & 1u) << 5));
     }
   }
 }
 
-template <int G, int kU, int MODE, int CH>
+template <int G, int kU, int MODE>
 __device__ __forceinline__ void fold(const Batch<kU>& bt, unsigned long long* Z,
                                      const float2* wf, float scale, int ls, int first) {
 #pragma unroll
   for (int g0 = 0; g0 < kU; g0 += 4) {
     if ((first + g0) * G >= ls) break;
-    fold_group<kU, MODE, CH>(bt, g0, Z, wf, scale);
+    fold_group<kU, MODE>(bt, g0, Z, wf, scale);
   }
 }
 
 // Entries g0 .. g0+3 (fewer in the last group) of batch `first` into the
 // same positions of `bt`; `whole`: the batch lies wholly inside the segment.
-template <int G, int kU>
+template <int G, int kU, typename E>
 __device__ __forceinline__ void fetch_group(Batch<kU>& bt, int g0, const float* sa,
-                                            const uint32_t* en, int ls, int lane, int first,
+                                            const E* en, int ls, int lane, int first,
                                             uint32_t own_off, bool whole) {
   constexpr int kG = 4;
   const int gn = kU - g0 < kG ? kU - g0 : kG;
@@ -334,9 +334,9 @@ __device__ __forceinline__ void fetch_group(Batch<kU>& bt, int g0, const float* 
 // group's registers are refilled with the same group of the next batch
 // right after the group is folded, so the next batch's loads are in flight
 // behind the rest of the folding, with no second buffer.
-template <int G, int kU, int MODE, int CH>
+template <int G, int kU, int MODE, typename E>
 __device__ __forceinline__ void fold_all(Batch<kU>& a, unsigned long long* Z, const float2* wf,
-                                         float scale, const float* sa, const uint32_t* en, int ls,
+                                         float scale, const float* sa, const E* en, int ls,
                                          int lane, uint32_t own_off) {
   for (int first = 0;; first += kU) {
     const int next = first + kU;
@@ -345,11 +345,11 @@ __device__ __forceinline__ void fold_all(Batch<kU>& a, unsigned long long* Z, co
       const bool whole = (next + kU) * G <= ls;
 #pragma unroll
       for (int g0 = 0; g0 < kU; g0 += 4) {
-        fold_group<kU, MODE, CH>(a, g0, Z, wf, scale);
+        fold_group<kU, MODE>(a, g0, Z, wf, scale);
         fetch_group<G, kU>(a, g0, sa, en, ls, lane, next, own_off, whole);
       }
     } else {
-      fold<G, kU, MODE, CH>(a, Z, wf, scale, ls, first);
+      fold<G, kU, MODE>(a, Z, wf, scale, ls, first);
       break;
     }
   }
@@ -416,12 +416,12 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
   for (int q = 0; q < 16; ++q) acc[q] = make_float2(0.f, 0.f);
   const float* sa0 = a.SA0 + (int64_t)t * a.m * a.Lrow0 + wv * a.Lcap0;
   const float* sa1 = a.SA1 + (int64_t)t * a.m * a.Lrow1 + wv * a.Lcap1;
-  const uint32_t* en0 = a.ent0 + (int64_t)t * a.Lrow0 + wv * a.Lcap0;
-  const uint32_t* en1 = a.ent1 + (int64_t)t * a.Lrow1 + wv * a.Lcap1;
+  const uint16_t* en0 = a.entp0 + (int64_t)t * a.Lrow0 + wv * a.Lcap0;
+  const uint16_t* en1 = a.entp1 + (int64_t)t * a.Lrow1 + wv * a.Lcap1;
   const int ls0 = a.lseg0[t], ls1 = a.lseg1[t];
   const float* cm0 = a.cmax0 + (int64_t)t * a.m;
   const float* cm1 = a.cmax1 + (int64_t)t * a.m;
-  const uint32_t own_off = (uint32_t)jbase * 8u;
+  const uint32_t own_off = (uint32_t)jbase * 8u;   // a pair entry too (parity 0)
   Batch<kU> bt;
   if (kb < ke) fetch<G, kU>(bt, sa0 + (int64_t)kb * a.Lrow0, en0, ls0, lane, 0, own_off);
   const float2* wf = nullptr;   // unused by the pair fold
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const float* sa = side == 0 ? sa0 + (int64_t)k * a.Lrow0 : sa1 + (int64_t)k * a.Lrow1;
-      const uint32_t* en = side == 0 ? en0 : en1;
+      const uint16_t* en = side == 0 ? en0 : en1;
       const int ls = side == 0 ? ls0 : ls1;
       // a slot of the pair gathers at most R/2 buckets: the bound of the
       // rows holds
@@ -442,7 +442,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
       const float scale = bound > 0.0f ? ldexpf(1.0f, 30 - ex) : 0.0f;
       const float inv = bound > 0.0f ? ldexpf(1.0f, ex - 30) : 0.0f;
       __builtin_amdgcn_s_setprio(1);
-      fold_all<G, kU, kFoldPair, C / 2>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      fold_all<G, kU, kFoldPair>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
       else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0, own_off);
       __builtin_amdgcn_s_setprio(0);
@@ -614,8 +614,8 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
       __builtin_amdgcn_wave_barrier();
       // the fold and the fetch run at raised wave priority (see fold_all)
       __builtin_amdgcn_s_setprio(1);
-      if (f1 == 0) fold_all<G, kU, kFoldRow0, C / 2>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
-      else fold_all<G, kU, kFoldRow, C / 2>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      if (f1 == 0) fold_all<G, kU, kFoldRow0>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      else fold_all<G, kU, kFoldRow>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
       // first batch of the next (side, k), in flight during the transform
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
       else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0, own_off);
@@ -692,6 +692,7 @@ hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc&
   FftArgs a;
   a.SA0 = sa.SA; a.SA1 = sb.SA;
   a.ent0 = sa.ent; a.ent1 = sb.ent;
+  a.entp0 = sa.entp; a.entp1 = sb.entp;
   a.lseg0 = sa.lseg; a.lseg1 = sb.lseg;
   a.cmax0 = sa.colmax; a.cmax1 = sb.colmax;
   a.Lcap0 = sa.Lcap; a.Lcap1 = sb.Lcap; a.Lrow0 = sa.Lrow; a.Lrow1 = sb.Lrow;

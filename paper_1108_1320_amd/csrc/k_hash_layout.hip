@@ -115,6 +115,7 @@ __global__ __launch_bounds__(1024) void k_segment_rank(const int32_t* __restrict
                                                        int64_t b, int log2c, int T, int G, int W, int Lcap,
                                                        int Lrow, int32_t* __restrict__ pos,
                                                        uint32_t* __restrict__ ent,
+                                                       uint16_t* __restrict__ entp,
                                                        int32_t* __restrict__ cntp,
                                                        int32_t* __restrict__ segcount,
                                                        int32_t* __restrict__ overflow) {
@@ -126,6 +127,7 @@ __global__ __launch_bounds__(1024) void k_segment_rank(const int32_t* __restrict
   const int32_t* cnt_t = cnt + (int64_t)t * b;
   int32_t* pos_t = pos + (int64_t)t * b;
   uint32_t* ent_t = ent + (int64_t)t * Lrow + (int64_t)w * Lcap;
+  uint16_t* entp_t = entp + (int64_t)t * Lrow + (int64_t)w * Lcap;
   int32_t* cntp_t = cntp + (int64_t)t * Lrow + (int64_t)w * Lcap;
   int base = 0;
   for (int64_t e0 = 0; e0 < nseg; e0 += 1024) {
@@ -149,6 +151,7 @@ __global__ __launch_bounds__(1024) void k_segment_rank(const int32_t* __restrict
       if (occ && rank < Lcap) {
         pos_t[u] = w * Lcap + rank;
         ent_t[rank] = fold_entry((uint32_t)u, log2c);
+        entp_t[rank] = pair_entry((uint32_t)u, log2c);
         cntp_t[rank] = c;
       } else {
         pos_t[u] = -1;
@@ -173,6 +176,7 @@ __global__ __launch_bounds__(1024) void k_segment_rank_chunks(const int32_t* __r
                                                               int64_t b, int log2c, int T, int G, int W,
                                                               int Lcap, int Lrow, int32_t* __restrict__ pos,
                                                               uint32_t* __restrict__ ent,
+                                                              uint16_t* __restrict__ entp,
                                                               int32_t* __restrict__ cntp,
                                                               int32_t* __restrict__ segcount,
                                                               int32_t* __restrict__ overflow) {
@@ -211,11 +215,13 @@ __global__ __launch_bounds__(1024) void k_segment_rank_chunks(const int32_t* __r
   const int rank = base + wave_pre[wv] + lrank;
   int32_t* pos_t = pos + (int64_t)t * b;
   uint32_t* ent_t = ent + (int64_t)t * Lrow + (int64_t)w * Lcap;
+  uint16_t* entp_t = entp + (int64_t)t * Lrow + (int64_t)w * Lcap;
   int32_t* cntp_t = cntp + (int64_t)t * Lrow + (int64_t)w * Lcap;
   if (valid) {
     if (occ && rank < Lcap) {
       pos_t[u] = w * Lcap + rank;
       ent_t[rank] = fold_entry((uint32_t)u, log2c);
+        entp_t[rank] = pair_entry((uint32_t)u, log2c);
       cntp_t[rank] = c;
     } else {
       pos_t[u] = -1;
@@ -230,6 +236,7 @@ __global__ __launch_bounds__(1024) void k_layout_finish(int W, int G, int Lcap, 
                                                         const int32_t* __restrict__ segcount,
                                                         int32_t* __restrict__ lseg,
                                                         uint32_t* __restrict__ ent,
+                                                        uint16_t* __restrict__ entp,
                                                         uint32_t* __restrict__ tab,
                                                         int32_t* __restrict__ cntp,
                                                         int32_t* __restrict__ moff) {
@@ -247,6 +254,7 @@ __global__ __launch_bounds__(1024) void k_layout_finish(int W, int G, int Lcap, 
   __syncthreads();
   const int L = s_l;
   uint32_t* ent_t = ent + (int64_t)t * Lrow;
+  uint16_t* entp_t = entp + (int64_t)t * Lrow;
   uint32_t* tab_t = tab + (int64_t)t * Lrow;
   int32_t* cntp_t = cntp + (int64_t)t * Lrow;
   int32_t* moff_t = moff + (int64_t)t * Lrow;
@@ -255,6 +263,7 @@ __global__ __launch_bounds__(1024) void k_layout_finish(int W, int G, int Lcap, 
     int sc = min(segcount[t * W + w], Lcap);
     for (int r = sc + tid; r < L; r += blockDim.x) {
       ent_t[w * Lcap + r] = pad_entry(w, G, r);
+      entp_t[w * Lcap + r] = (uint16_t)pad_entry(w, G, r);
       tab_t[w * Lcap + r] = CMM_PAD_TAB;
       cntp_t[w * Lcap + r] = 0;
     }
@@ -331,14 +340,14 @@ hipError_t launch_layout(const Geometry& g, SideDesc& sd, int32_t* overflow, hip
   const int64_t nchunks = (g.b / g.W + 1023) / 1024;
   if (nchunks <= kRankChunks)
     hipLaunchKernelGGL(k_segment_rank_chunks, dim3((unsigned)nchunks, g.W, g.d), dim3(1024), 0, s, sd.cnt,
-                       g.b, g.log2c, g.T, g.G, g.W, sd.Lcap, sd.Lrow, sd.pos, sd.ent, sd.cntp,
+                       g.b, g.log2c, g.T, g.G, g.W, sd.Lcap, sd.Lrow, sd.pos, sd.ent, sd.entp, sd.cntp,
                        sd.segcount, overflow);
   else
     hipLaunchKernelGGL(k_segment_rank, dim3(g.W, g.d), dim3(1024), 0, s, sd.cnt, g.b, g.log2c, g.T, g.G,
-                       g.W, sd.Lcap, sd.Lrow, sd.pos, sd.ent, sd.cntp, sd.segcount, overflow);
+                       g.W, sd.Lcap, sd.Lrow, sd.pos, sd.ent, sd.entp, sd.cntp, sd.segcount, overflow);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_layout_finish, dim3(g.d), dim3(1024), 0, s, g.W, g.G, sd.Lcap, sd.Lrow,
-                     sd.segcount, sd.lseg, sd.ent, sd.tab, sd.cntp, sd.moff);
+                     sd.segcount, sd.lseg, sd.ent, sd.entp, sd.tab, sd.cntp, sd.moff);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = launch_fill_i32(sd.fill, (int64_t)g.d * sd.Lrow, 0, s)) != hipSuccess) return e;
   int64_t total = (int64_t)g.d * sd.n;
