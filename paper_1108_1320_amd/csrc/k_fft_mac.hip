@@ -93,14 +93,28 @@ template <int L> struct FftShape {
   static constexpr int NMID = (S >= 3 && !kRegMid) ? tmoff(S - 1) : 0;
 };
 
-// Byte offset of the write of output r in stages 0 and 1 of a radix-16
+// LDS (address space 3) views of the dynamic shared array: 32-bit byte
+// addresses, so that an address formed by xor is used as it is.  The
+// spectral kernels declare no static shared memory (prepare_fft_mac checks
+// it), so the dynamic array starts at address 0 and every buffer in it
+// starts at a multiple of 2048 bytes (the only bits the stage-write xors
+// touch are bits 3..10).
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+__device__ __forceinline__ uint32_t lds_addr(const float2* p) {
+  return (uint32_t)(uintptr_t)(const lds_u64*)p;
+}
+__device__ __forceinline__ void lds_store(uint32_t addr, float2 v) {
+  *(lds_u64*)(uintptr_t)addr = __builtin_bit_cast(unsigned long long, v);
+}
+
+// LDS address of the write of output r in stages 0 and 1 of a radix-16
 // row: position sw(16 j + r) for stage 0 and sw(256 (j / 16) + (j mod 16) +
 // 16 r) for stage 1.  The swizzle only mixes bits 4..7 into bits 0..3, so
 // both are one base per thread xor a multiple of r: 8 r and 136 r.  The base
-// is made opaque so that it is formed once per stage instead of 16 offsets
-// being held in registers across the loop.
-template <int s> __device__ __forceinline__ int stage_write_base(int j) {
-  int A = s == 0 ? 128 * j + 8 * (j & 15) : 2048 * (j >> 4) + 8 * (j & 15);
+// (with the buffer's own address) is made opaque so that it is formed once
+// per stage instead of 16 addresses being held in registers across the loop.
+template <int s> __device__ __forceinline__ uint32_t stage_write_base(const float2* buf, int j) {
+  uint32_t A = lds_addr(buf) + (uint32_t)(s == 0 ? 128 * j + 8 * (j & 15) : 2048 * (j >> 4) + 8 * (j & 15));
   asm volatile("" : "+v"(A));
   return A;
 }
@@ -157,10 +171,10 @@ template <int L, int s> struct Stage {
     if constexpr (s < F::S - 1) {
       if constexpr (s == 0 && F::S % 2 == 0) __syncthreads();
       if constexpr (Rs == 16 && (s == 0 || Ns == 16)) {
-        const int A = stage_write_base<s>(j);
-        constexpr int K = s == 0 ? 8 : 136;
+        const uint32_t A = stage_write_base<s>(bout, j);
+        constexpr uint32_t K = s == 0 ? 8 : 136;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) at_byte(bout, (uint32_t)(A ^ (K * r))) = v[r];
+        for (int r = 0; r < 16; ++r) lds_store(A ^ (K * (uint32_t)r), v[r]);
       } else {
 #pragma unroll
         for (int mi = 0; mi < BPT; ++mi) {
@@ -726,7 +740,12 @@ hipError_t prepare_fft_mac() {
   const void* fns[] = {CMM_FNS(k_fft_mac), CMM_FNS(k_fft_mac_pair)};
 #undef CMM_FNS
   for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    // the stage-write addressing needs the dynamic array at address 0
+    hipFuncAttributes at;
+    hipError_t e = hipFuncGetAttributes(&at, f);
+    if (e != hipSuccess) return e;
+    if (at.sharedSizeBytes != 0) return hipErrorInvalidDeviceFunction;
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
