@@ -96,9 +96,10 @@ template <int L> struct FftShape {
 // LDS (address space 3) views of the dynamic shared array: 32-bit byte
 // addresses, so that an address formed by xor is used as it is.  The
 // spectral kernels declare no static shared memory (prepare_fft_mac checks
-// it), so the dynamic array starts at address 0 and every buffer in it
-// starts at a multiple of 2048 bytes (the only bits the stage-write xors
-// touch are bits 3..10).
+// it), so the dynamic array starts at address 0, and the two transform
+// buffers at 0 and 8C bytes: multiples of 2048 bytes for the row lengths
+// whose stages write through xor-formed addresses (256 and 4096 points),
+// and the xors touch bits 3..10 only.
 typedef __attribute__((address_space(3))) unsigned long long lds_u64;
 __device__ __forceinline__ uint32_t lds_addr(const float2* p) {
   return (uint32_t)(uintptr_t)(const lds_u64*)p;
