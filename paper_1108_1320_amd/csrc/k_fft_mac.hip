@@ -29,6 +29,8 @@
 // sums are exact integer (fixed-point) sums, independent of their order.
 #include "cmm_internal.h"
 #include "cmm_dft.h"
+#include <algorithm>
+#include <cmath>
 
 namespace cmm {
 
@@ -282,10 +284,9 @@ enum { kFoldRow0 = 0, kFoldRow = 1, kFoldPair = 2 };
 // wave-uniform test; inside a group there is no branch, so the weight reads
 // issue together.  Padding entries carry value 0 and an own slot of the
 // wave.
-template <int kU, int MODE>
+template <int kU, int MODE, int kG>
 __device__ __forceinline__ void fold_group(const Batch<kU>& bt, int g0, unsigned long long* Z,
                                            const float2* wf, float scale) {
-  constexpr int kG = 4;
   const int gn = kU - g0 < kG ? kU - g0 : kG;
   float2 w[kG];
   if constexpr (MODE == kFoldRow) {
@@ -313,23 +314,22 @@ __device__ __forceinline__ void fold_group(const Batch<kU>& bt, int g0, unsigned
   }
 }
 
-template <int G, int kU, int MODE>
+template <int G, int kU, int MODE, int kG>
 __device__ __forceinline__ void fold(const Batch<kU>& bt, unsigned long long* Z,
                                      const float2* wf, float scale, int ls, int first) {
 #pragma unroll
-  for (int g0 = 0; g0 < kU; g0 += 4) {
+  for (int g0 = 0; g0 < kU; g0 += kG) {
     if ((first + g0) * G >= ls) break;
-    fold_group<kU, MODE>(bt, g0, Z, wf, scale);
+    fold_group<kU, MODE, kG>(bt, g0, Z, wf, scale);
   }
 }
 
 // Entries g0 .. g0+3 (fewer in the last group) of batch `first` into the
 // same positions of `bt`; `whole`: the batch lies wholly inside the segment.
-template <int G, int kU, typename E>
+template <int G, int kU, int kG, typename E>
 __device__ __forceinline__ void fetch_group(Batch<kU>& bt, int g0, const float* sa,
                                             const E* en, int ls, int lane, int first,
                                             uint32_t own_off, bool whole) {
-  constexpr int kG = 4;
   const int gn = kU - g0 < kG ? kU - g0 : kG;
 #pragma unroll
   for (int i = 0; i < kG; ++i) {
@@ -349,7 +349,7 @@ __device__ __forceinline__ void fetch_group(Batch<kU>& bt, int g0, const float* 
 // group's registers are refilled with the same group of the next batch
 // right after the group is folded, so the next batch's loads are in flight
 // behind the rest of the folding, with no second buffer.
-template <int G, int kU, int MODE, typename E>
+template <int G, int kU, int MODE, int kG, typename E>
 __device__ __forceinline__ void fold_all(Batch<kU>& a, unsigned long long* Z, const float2* wf,
                                          float scale, const float* sa, const E* en, int ls,
                                          int lane, uint32_t own_off) {
@@ -359,12 +359,12 @@ __device__ __forceinline__ void fold_all(Batch<kU>& a, unsigned long long* Z, co
       // every group of this batch lies inside the segment
       const bool whole = (next + kU) * G <= ls;
 #pragma unroll
-      for (int g0 = 0; g0 < kU; g0 += 4) {
-        fold_group<kU, MODE>(a, g0, Z, wf, scale);
-        fetch_group<G, kU>(a, g0, sa, en, ls, lane, next, own_off, whole);
+      for (int g0 = 0; g0 < kU; g0 += kG) {
+        fold_group<kU, MODE, kG>(a, g0, Z, wf, scale);
+        fetch_group<G, kU, kG>(a, g0, sa, en, ls, lane, next, own_off, whole);
       }
     } else {
-      fold<G, kU, MODE>(a, Z, wf, scale, ls, first);
+      fold<G, kU, MODE, kG>(a, Z, wf, scale, ls, first);
       break;
     }
   }
@@ -373,7 +373,7 @@ __device__ __forceinline__ void fold_all(Batch<kU>& a, unsigned long long* Z, co
 // One block per (repetition t, k-split ks): the row pair {0, R/2} (R > 1;
 // see the fold modes above).  A kernel of its own, launched beside the row
 // kernel, so that each keeps its own register allocation.
-template <int L>
+template <int L, int kG>
 __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
   typedef FftShape<L> F;
   const int bid = blockIdx.x;
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
       const float scale = bound > 0.0f ? ldexpf(1.0f, 30 - ex) : 0.0f;
       const float inv = bound > 0.0f ? ldexpf(1.0f, ex - 30) : 0.0f;
       __builtin_amdgcn_s_setprio(1);
-      fold_all<G, kU, kFoldPair>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      fold_all<G, kU, kFoldPair, kG>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
       else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0, own_off);
       __builtin_amdgcn_s_setprio(0);
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
 // nrow blocks per (repetition, k-split): rows f1 = roff .. roff + nrow - 1,
 // i.e. 1 .. R/2 - 1 when R > 1 (the pair kernel computes rows 0 and R/2)
 // and row 0 alone when R == 1.
-template <int L>
+template <int L, int kG>
 __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   typedef FftShape<L> F;
   constexpr int C = F::C, T = F::T, G = F::G, kU = F::U;
@@ -629,8 +629,8 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
       __builtin_amdgcn_wave_barrier();
       // the fold and the fetch run at raised wave priority (see fold_all)
       __builtin_amdgcn_s_setprio(1);
-      if (f1 == 0) fold_all<G, kU, kFoldRow0>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
-      else fold_all<G, kU, kFoldRow>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      if (f1 == 0) fold_all<G, kU, kFoldRow0, kG>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      else fold_all<G, kU, kFoldRow, kG>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
       // first batch of the next (side, k), in flight during the transform
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
       else if (k + 1 < ke) fetch<G, kU>(bt, sa0 + (int64_t)(k + 1) * a.Lrow0, en0, ls0, lane, 0, own_off);
@@ -673,8 +673,8 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
 // The pair kernel has one block per (repetition, k-split), an eighth of the
 // work at R = 16; alone it would leave most of the chip idle for its last
 // blocks, so with `ov` it runs on the second stream beside the row kernel.
-template <int L>
-static hipError_t launch_L(FftArgs a, const Geometry& g, hipStream_t s, const Overlap* ov) {
+template <int L, int kG>
+static hipError_t launch_LG(FftArgs a, const Geometry& g, hipStream_t s, const Overlap* ov) {
   typedef FftShape<L> F;
   const size_t lds = (size_t)(2 * F::C + F::NMID + 16 * a.R) * sizeof(float2);
   hipError_t e = hipSuccess;
@@ -686,7 +686,7 @@ static hipError_t launch_L(FftArgs a, const Geometry& g, hipStream_t s, const Ov
   if (g.R > 1) {
     a.nwg = g.d * g.KS;
     a.remap = (a.nwg % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL(k_fft_mac_pair<L>, dim3(a.nwg), dim3(F::T), lds, fork ? ov->aux : s, a);
+    hipLaunchKernelGGL((k_fft_mac_pair<L, kG>), dim3(a.nwg), dim3(F::T), lds, fork ? ov->aux : s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (fork && (e = hipEventRecord(ov->join, ov->aux)) != hipSuccess) return e;
@@ -695,11 +695,25 @@ static hipError_t launch_L(FftArgs a, const Geometry& g, hipStream_t s, const Ov
   if (a.nrow > 0) {
     a.nwg = g.d * g.KS * a.nrow;
     a.remap = (a.nwg % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL(k_fft_mac<L>, dim3(a.nwg), dim3(F::T), lds, s, a);
+    hipLaunchKernelGGL((k_fft_mac<L, kG>), dim3(a.nwg), dim3(F::T), lds, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (fork) e = hipStreamWaitEvent(s, ov->join, 0);
   return e;
+}
+
+// Fold group size: 8 entries when a wave's segment is expected to take
+// well over one batch of U entries per lane (more refetched entries in
+// flight per group then pay), else 4 (one batch, or a short second one,
+// where groups of 8 would fold more padding).  Both measured at 4096-point
+// rows.  The expected segment length is the expected number of non-empty
+// buckets of the fuller side over the W segments of a repetition.
+template <int L>
+static hipError_t launch_L(FftArgs a, const Geometry& g, int64_t n_max, hipStream_t s, const Overlap* ov) {
+  typedef FftShape<L> F;
+  const double nb = (double)g.b * -std::expm1((double)n_max * std::log1p(-1.0 / (double)g.b));
+  const bool several = nb / g.W > 1.5 * F::U * F::G;
+  return several ? launch_LG<L, 8>(a, g, s, ov) : launch_LG<L, 4>(a, g, s, ov);
 }
 
 hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc& sb,
@@ -714,17 +728,18 @@ hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc&
   a.tw = tw32; a.Ppart = Ppart; a.b = g.b;
   a.R = g.R; a.rows = g.rows; a.d = g.d; a.m = g.m; a.KS = g.KS;
   a.nrow = 1; a.roff = 0; a.nwg = 0; a.remap = 0;
+  const int64_t n_max = std::max<int64_t>(sa.n, sb.n);
   switch (g.log2c) {
-    case 4: return launch_L<4>(a, g, s, ov);
-    case 5: return launch_L<5>(a, g, s, ov);
-    case 6: return launch_L<6>(a, g, s, ov);
-    case 7: return launch_L<7>(a, g, s, ov);
-    case 8: return launch_L<8>(a, g, s, ov);
-    case 9: return launch_L<9>(a, g, s, ov);
-    case 10: return launch_L<10>(a, g, s, ov);
-    case 11: return launch_L<11>(a, g, s, ov);
-    case 12: return launch_L<12>(a, g, s, ov);
-    case 13: return launch_L<13>(a, g, s, ov);
+    case 4: return launch_L<4>(a, g, n_max, s, ov);
+    case 5: return launch_L<5>(a, g, n_max, s, ov);
+    case 6: return launch_L<6>(a, g, n_max, s, ov);
+    case 7: return launch_L<7>(a, g, n_max, s, ov);
+    case 8: return launch_L<8>(a, g, n_max, s, ov);
+    case 9: return launch_L<9>(a, g, n_max, s, ov);
+    case 10: return launch_L<10>(a, g, n_max, s, ov);
+    case 11: return launch_L<11>(a, g, n_max, s, ov);
+    case 12: return launch_L<12>(a, g, n_max, s, ov);
+    case 13: return launch_L<13>(a, g, n_max, s, ov);
     default: return hipErrorInvalidValue;
   }
 }
@@ -732,13 +747,14 @@ hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc&
 // Raise the dynamic LDS limit of every row length to 160 KB (done once per
 // context, outside any graph capture).
 hipError_t prepare_fft_mac() {
-#define CMM_FNS(K) \
-  reinterpret_cast<const void*>(&K<4>), reinterpret_cast<const void*>(&K<5>), \
-  reinterpret_cast<const void*>(&K<6>), reinterpret_cast<const void*>(&K<7>), \
-  reinterpret_cast<const void*>(&K<8>), reinterpret_cast<const void*>(&K<9>), \
-  reinterpret_cast<const void*>(&K<10>), reinterpret_cast<const void*>(&K<11>), \
-  reinterpret_cast<const void*>(&K<12>), reinterpret_cast<const void*>(&K<13>)
-  const void* fns[] = {CMM_FNS(k_fft_mac), CMM_FNS(k_fft_mac_pair)};
+#define CMM_FNS(K, G) \
+  reinterpret_cast<const void*>(&K<4, G>), reinterpret_cast<const void*>(&K<5, G>), \
+  reinterpret_cast<const void*>(&K<6, G>), reinterpret_cast<const void*>(&K<7, G>), \
+  reinterpret_cast<const void*>(&K<8, G>), reinterpret_cast<const void*>(&K<9, G>), \
+  reinterpret_cast<const void*>(&K<10, G>), reinterpret_cast<const void*>(&K<11, G>), \
+  reinterpret_cast<const void*>(&K<12, G>), reinterpret_cast<const void*>(&K<13, G>)
+  const void* fns[] = {CMM_FNS(k_fft_mac, 4), CMM_FNS(k_fft_mac_pair, 4), CMM_FNS(k_fft_mac, 8),
+                       CMM_FNS(k_fft_mac_pair, 8)};
 #undef CMM_FNS
   for (const void* f : fns) {
     // the stage-write addressing needs the dynamic array at address 0
