@@ -41,6 +41,16 @@
  * - fp8 scales are per hashed index (scaleA[n1], scaleB[n3]): one float per
  *   column of each stored k-major array, multiplied into every value of
  *   that index before it is hashed.
+ * - Values must be finite and of float32-friendly size.  Each column a_k
+ *   and row b_k is count-sketched and transformed in float32 (its fold into
+ *   the transform rows is 30-bit fixed point relative to its largest
+ *   |value|), and the products of two spectra are float32; the k-sum and
+ *   the inverse transform are float64.  So max|a_k| * max|b_k| * n1 * n3
+ *   must stay below about 1e37, and a column or row whose largest |value|
+ *   is nonzero but below about 1e-29 lies outside its fixed-point scale
+ *   (its contribution is then lost; such terms are below float32's range
+ *   in the products anyway).  Errors are relative to the largest sketch
+ *   entries.
  * - Objects are library-owned: free sketches with cmm_sketch_free() before
  *   destroying their context with cmm_ctx_destroy().
  * - A context and its sketches are used by one host thread at a time (the
