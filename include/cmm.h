@@ -47,10 +47,10 @@
  *   |value|), and the products of two spectra are float32; the k-sum and
  *   the inverse transform are float64.  So max|a_k| * max|b_k| * n1 * n3
  *   must stay below about 1e37, and a column or row whose largest |value|
- *   is nonzero but below about 1e-29 lies outside its fixed-point scale
- *   (its contribution is then lost; such terms are below float32's range
- *   in the products anyway).  Errors are relative to the largest sketch
- *   entries.
+ *   is nonzero but below about 1e-29 lies outside the range of its
+ *   fixed-point scale, and its fold is then meaningless (its terms would be
+ *   below float32's range in the products anyway).  Errors are relative to
+ *   the largest sketch entries.
  * - Objects are library-owned: free sketches with cmm_sketch_free() before
  *   destroying their context with cmm_ctx_destroy().
  * - A context and its sketches are used by one host thread at a time (the
