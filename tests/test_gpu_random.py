@@ -3,6 +3,7 @@ operand formats, strides, the diagonal flag and stored tunings drawn at
 random (a fixed seed, so every run checks the same cases), each sketch
 against the float64 oracle on the values the GPU multiplies, and the top-K
 estimates against oracle decodes."""
+import os
 import sys
 
 import numpy as np
@@ -14,7 +15,9 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 REL_TOL = 1e-5
-N_CASES = 120
+# a longer or different sweep can be run with CMM_RANDOM_CASES / CMM_RANDOM_SEED
+N_CASES = int(os.environ.get("CMM_RANDOM_CASES", "120"))
+SWEEP_SEED = int(os.environ.get("CMM_RANDOM_SEED", "20261203"))
 
 
 def _say(msg):
@@ -30,7 +33,7 @@ def ctx(cmm):
 
 
 def _cases():
-    g = np.random.default_rng(20261203)
+    g = np.random.default_rng(SWEEP_SEED)
     out = []
     for q in range(N_CASES):
         n1 = int(np.exp(g.uniform(0, np.log(3000))))
