@@ -78,10 +78,19 @@ def test_random_parity(cmm, ctx, case):
     c = sk.c()
     c_ref, tabs, _ = O.run(Aq.T, Bq, b, d, seed, subtract_diag=diag)
     scale = np.abs(c_ref).max()
+    full = None
     for t in range(d):
         nrm = np.linalg.norm(c_ref[t])
         if nrm <= 1e-12 * max(scale, 1e-300):
-            assert np.abs(c[t]).max() <= 1e-6 * max(scale, 1.0)
+            # the reference vanishes, e.g. when every term of the product lies
+            # on the removed diagonal (n1 = n3 = 1): the float32 path's error
+            # is then relative to the sketch before the removal
+            if full is None:
+                full = scale
+                if diag:
+                    c_full, _, _ = O.run(Aq.T, Bq, b, d, seed, subtract_diag=False)
+                    full = max(full, float(np.abs(c_full).max()))
+            assert np.abs(c[t]).max() <= 1e-6 * max(full, 1.0)
         else:
             assert np.linalg.norm(c[t] - c_ref[t]) / nrm <= REL_TOL, (t, np.linalg.norm(c[t] - c_ref[t]) / nrm)
     # returned top-K values are the estimates at the returned positions
