@@ -78,28 +78,40 @@ def test_random_parity(cmm, ctx, case):
     c = sk.c()
     c_ref, tabs, _ = O.run(Aq.T, Bq, b, d, seed, subtract_diag=diag)
     scale = np.abs(c_ref).max()
-    full = None
+    # With the diagonal removed, the float32 spectral path's error scales with
+    # the sketch before the removal (the removal itself is exact), which can
+    # be far larger than what remains (n1 = n3 = 1 leaves nothing): the
+    # allowed error is relative to that sketch.
+    c_full = O.run(Aq.T, Bq, b, d, seed, subtract_diag=False)[0] if diag else c_ref
+    full_scale = max(scale, float(np.abs(c_full).max()))
     for t in range(d):
-        nrm = np.linalg.norm(c_ref[t])
-        if nrm <= 1e-12 * max(scale, 1e-300):
-            # the reference vanishes, e.g. when every term of the product lies
-            # on the removed diagonal (n1 = n3 = 1): the float32 path's error
-            # is then relative to the sketch before the removal
-            if full is None:
-                full = scale
-                if diag:
-                    c_full, _, _ = O.run(Aq.T, Bq, b, d, seed, subtract_diag=False)
-                    full = max(full, float(np.abs(c_full).max()))
-            assert np.abs(c[t]).max() <= 1e-6 * max(full, 1.0)
+        nrm = max(np.linalg.norm(c_ref[t]), np.linalg.norm(c_full[t]))
+        if nrm <= 1e-12 * max(full_scale, 1e-300):
+            assert np.abs(c[t]).max() <= 1e-6 * max(full_scale, 1.0)
         else:
-            assert np.linalg.norm(c[t] - c_ref[t]) / nrm <= REL_TOL, (t, np.linalg.norm(c[t] - c_ref[t]) / nrm)
+            rel = np.linalg.norm(c[t] - c_ref[t]) / nrm
+            assert rel <= REL_TOL, (t, rel)
     # returned top-K values are the estimates at the returned positions
     mode = "upper" if diag and n1 > 1 else "all"
     dom = n1 * (n1 - 1) // 2 if mode == "upper" else n1 * n3
     K = int(min(8, dom))
     if K >= 1:
-        oi, oj, ov = sk.topk(K, mode)
+        try:
+            oi, oj, ov = sk.topk(K, mode)
+        except cmm.CmmError as e:
+            # the documented limit: more than 4096 estimates tied at the K-th
+            # magnitude (small b and d put whole buckets of candidates on one
+            # value); the tie count is checked on the oracle's estimates
+            assert e.code == -4, e
+            ii, jj = O.candidates(mode, n1, n3)
+            mags = np.abs(O.decode(c_ref, tabs, ii, jj))
+            kth = np.sort(mags)[::-1][K - 1]
+            assert np.count_nonzero(mags == kth) > 4096, (K, kth)
+            return
         if mode == "upper":
             assert np.all(oi < oj)
         err = np.abs(c.astype(np.float64) - c_ref).max()
-        assert np.abs(ov - O.decode(c_ref, tabs, oi, oj)).max() <= err + 1e-6 * max(scale, 1e-30)
+        # the decoded values are float32 (one rounding, and one more for the
+        # mean of the two middle values when d is even)
+        rnd = 2.0 ** -22 * float(np.abs(ov).max())
+        assert np.abs(ov - O.decode(c_ref, tabs, oi, oj)).max() <= err + rnd + 1e-6 * max(scale, 1e-30)
