@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 REL_TOL = 1e-5
 # a longer or different sweep can be run with CMM_RANDOM_CASES / CMM_RANDOM_SEED
-N_CASES = int(os.environ.get("CMM_RANDOM_CASES", "120"))
+N_CASES = int(os.environ.get("CMM_RANDOM_CASES", "500"))
 SWEEP_SEED = int(os.environ.get("CMM_RANDOM_SEED", "20261203"))
 
 
