@@ -538,7 +538,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
 // nrow blocks per (repetition, k-split): rows f1 = roff .. roff + nrow - 1,
 // i.e. 1 .. R/2 - 1 when R > 1 (the pair kernel computes rows 0 and R/2)
 // and row 0 alone when R == 1.
-template <int L, int kG>
+template <int L, int kG, bool kRow0>
 __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   typedef FftShape<L> F;
   constexpr int C = F::C, T = F::T, G = F::G, kU = F::U;
@@ -629,7 +629,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
       __builtin_amdgcn_wave_barrier();
       // the fold and the fetch run at raised wave priority (see fold_all)
       __builtin_amdgcn_s_setprio(1);
-      if (f1 == 0) fold_all<G, kU, kFoldRow0, kG>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
+      if constexpr (kRow0) fold_all<G, kU, kFoldRow0, kG>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
       else fold_all<G, kU, kFoldRow, kG>(bt, Z, wf, scale, sa, en, ls, lane, own_off);
       // first batch of the next (side, k), in flight during the transform
       if (side == 0) fetch<G, kU>(bt, sa1 + (int64_t)k * a.Lrow1, en1, ls1, lane, 0, own_off);
@@ -638,8 +638,8 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
       __builtin_amdgcn_wave_barrier();
       // the slot factor omega_b^(f1 j) (1 in row 0) and the fixed-point unit
       // multiply every input of stage 0
-      const float2 pre = f1 != 0 ? make_float2(sj.x * inv, sj.y * inv) : make_float2(inv, 0.0f);
-      if (f1 != 0) {
+      const float2 pre = !kRow0 ? make_float2(sj.x * inv, sj.y * inv) : make_float2(inv, 0.0f);
+      if constexpr (!kRow0) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
           const int2 zi = unpack2(Z[own<T>(jbase, j, q)]);
@@ -695,7 +695,8 @@ static hipError_t launch_LG(FftArgs a, const Geometry& g, hipStream_t s, const O
   if (a.nrow > 0) {
     a.nwg = g.d * g.KS * a.nrow;
     a.remap = (a.nwg % 8 == 0) ? 1 : 0;
-    hipLaunchKernelGGL((k_fft_mac<L, kG>), dim3(a.nwg), dim3(F::T), lds, s, a);
+    if (g.R > 1) hipLaunchKernelGGL((k_fft_mac<L, kG, false>), dim3(a.nwg), dim3(F::T), lds, s, a);
+    else hipLaunchKernelGGL((k_fft_mac<L, 4, true>), dim3(a.nwg), dim3(F::T), lds, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (fork) e = hipStreamWaitEvent(s, ov->join, 0);
@@ -747,14 +748,14 @@ hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc&
 // Raise the dynamic LDS limit of every row length to 160 KB (done once per
 // context, outside any graph capture).
 hipError_t prepare_fft_mac() {
-#define CMM_FNS(K, G) \
-  reinterpret_cast<const void*>(&K<4, G>), reinterpret_cast<const void*>(&K<5, G>), \
-  reinterpret_cast<const void*>(&K<6, G>), reinterpret_cast<const void*>(&K<7, G>), \
-  reinterpret_cast<const void*>(&K<8, G>), reinterpret_cast<const void*>(&K<9, G>), \
-  reinterpret_cast<const void*>(&K<10, G>), reinterpret_cast<const void*>(&K<11, G>), \
-  reinterpret_cast<const void*>(&K<12, G>), reinterpret_cast<const void*>(&K<13, G>)
-  const void* fns[] = {CMM_FNS(k_fft_mac, 4), CMM_FNS(k_fft_mac_pair, 4), CMM_FNS(k_fft_mac, 8),
-                       CMM_FNS(k_fft_mac_pair, 8)};
+#define CMM_FNS(K, ...) \
+  reinterpret_cast<const void*>(&K<4, __VA_ARGS__>), reinterpret_cast<const void*>(&K<5, __VA_ARGS__>), \
+  reinterpret_cast<const void*>(&K<6, __VA_ARGS__>), reinterpret_cast<const void*>(&K<7, __VA_ARGS__>), \
+  reinterpret_cast<const void*>(&K<8, __VA_ARGS__>), reinterpret_cast<const void*>(&K<9, __VA_ARGS__>), \
+  reinterpret_cast<const void*>(&K<10, __VA_ARGS__>), reinterpret_cast<const void*>(&K<11, __VA_ARGS__>), \
+  reinterpret_cast<const void*>(&K<12, __VA_ARGS__>), reinterpret_cast<const void*>(&K<13, __VA_ARGS__>)
+  const void* fns[] = {CMM_FNS(k_fft_mac, 4, false), CMM_FNS(k_fft_mac, 4, true), CMM_FNS(k_fft_mac, 8, false),
+                       CMM_FNS(k_fft_mac_pair, 4), CMM_FNS(k_fft_mac_pair, 8)};
 #undef CMM_FNS
   for (const void* f : fns) {
     // the stage-write addressing needs the dynamic array at address 0
