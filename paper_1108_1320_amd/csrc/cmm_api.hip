@@ -891,7 +891,7 @@ int autotune_class(cmm_ctx* c, int64_t n1, int64_t m, int64_t n3, int64_t b, int
   std::vector<std::tuple<int, int, int>> seen{shape(cur)};
   for (int axis = 0; axis < 3 && rc == CMM_OK; ++axis) {
     const std::vector<int> vals = axis == 0 ? std::vector<int>{10, 11, 12, 13}
-                                : axis == 1 ? std::vector<int>{32, 64, 128}
+                                : axis == 1 ? std::vector<int>{32, 48, 64, 128}
                                             : std::vector<int>{512, 1024, 2048, 4096};
     const bool cs_only = axis == 2;
     const cmm::Tuning base = cur;
