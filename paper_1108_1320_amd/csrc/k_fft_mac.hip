@@ -48,6 +48,18 @@ template <int T> __device__ __forceinline__ int own(int jbase, int j, int q) {
   else return sw(j + T * q);
 }
 
+// Workgroups are dealt to the eight XCDs in turn (XCD = block id mod 8), and
+// each XCD has its own L2.  Logical tile order puts the rows of one
+// (repetition, k-range) next to each other, and they read the same
+// sketches, so XCD x is given one contiguous range of logical tiles: the
+// first nwg mod 8 XCDs take nwg div 8 + 1 tiles and the others nwg div 8.
+// A bijection on [0, nwg) for every grid size.
+__device__ __forceinline__ int xcd_tile(int bid, int nwg) {
+  const int x = bid & 7, i = bid >> 3;
+  const int q = nwg >> 3, r = nwg & 7;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
 struct FftArgs {
   const float* SA0; const float* SA1;
   const uint32_t* ent0; const uint32_t* ent1;
@@ -377,7 +389,7 @@ template <int L, int kG>
 __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
   typedef FftShape<L> F;
   const int bid = blockIdx.x;
-  const int logical = a.remap ? (bid & 7) * (a.nwg >> 3) + (bid >> 3) : bid;
+  const int logical = a.remap ? xcd_tile(bid, a.nwg) : bid;
   const int ks = logical % a.KS;
   const int t = logical / a.KS;
   constexpr int C = F::C, T = F::T, G = F::G, kU = F::U;
@@ -550,7 +562,7 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   static_assert(F::S <= 4, "at most two middle stages");
 
   const int bid = blockIdx.x;
-  const int logical = a.remap ? (bid & 7) * (a.nwg >> 3) + (bid >> 3) : bid;
+  const int logical = a.remap ? xcd_tile(bid, a.nwg) : bid;
   const int f1 = logical % a.nrow + a.roff;
   const int tmp = logical / a.nrow;
   const int ks = tmp % a.KS;
@@ -685,7 +697,7 @@ static hipError_t launch_LG(FftArgs a, const Geometry& g, hipStream_t s, const O
   }
   if (g.R > 1) {
     a.nwg = g.d * g.KS;
-    a.remap = (a.nwg % 8 == 0) ? 1 : 0;
+    a.remap = 1;
     hipLaunchKernelGGL((k_fft_mac_pair<L, kG>), dim3(a.nwg), dim3(F::T), lds, fork ? ov->aux : s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
@@ -694,7 +706,7 @@ static hipError_t launch_LG(FftArgs a, const Geometry& g, hipStream_t s, const O
   a.roff = g.R > 1 ? 1 : 0;
   if (a.nrow > 0) {
     a.nwg = g.d * g.KS * a.nrow;
-    a.remap = (a.nwg % 8 == 0) ? 1 : 0;
+    a.remap = 1;
     if (g.R > 1) hipLaunchKernelGGL((k_fft_mac<L, kG, false>), dim3(a.nwg), dim3(F::T), lds, s, a);
     else hipLaunchKernelGGL((k_fft_mac<L, 4, true>), dim3(a.nwg), dim3(F::T), lds, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
