@@ -94,6 +94,9 @@ def parse():
     p.add_argument("--replay-trace", type=int, default=0, metavar="N",
                    help="build the batched workload's graph, then run N graph replays 100 ms apart "
                         "(no top-K) so that a kernel trace can separate one replay's dispatches")
+    p.add_argument("--tune-cache", type=str, default=None, metavar="PATH",
+                   help="with --replay-trace: load the batch's size-class geometry from PATH if it exists, "
+                        "else autotune and save it there (so counter runs replay the same launches)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -291,7 +294,7 @@ def run_batched(ctx, steps, warmup, with_oracle=True):
         "topk_ms_per_step": round(dec_ms / max(steps, 1), 4),
         "standalone_sequential_sketch_ms": round(alone_ms, 3),
         "input_bytes": input_bytes, "products": len(ws), "size_classes": len(classes),
-        "tuning": {f"b={b},n<={n}": list(ctx.tuning(n, n, n, b, 5, "bf16")) for b, n in classes},
+        "tuning": batched_tuning(ctx, classes),
         "create_s": round(create_s, 2), "generate_s": round(gen_s, 2),
         "planted_recall": round(hits / sum(len(w.planted) for w in ws), 4),
     }
@@ -499,17 +502,43 @@ def stream_ceiling(ctx, gib=1.0, reps=10):
     return out
 
 
+def batched_tuning(ctx, classes):
+    """Geometry (log2c, kmax, cs_blocks) of each size class of the batch."""
+    return {f"b={b},n<={n}": list(ctx.tuning(n, n, n, b, 5, "bf16")) for b, n in classes}
+
+
+def batched_traffic_record(tuning):
+    """HBM bytes of the spectral kernels over one graph replay of the batched
+    form, from the committed rocprofv3 counter summary, if it was taken with
+    the same per-class geometry and the current kernel source (else None)."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", "fft_mac_traffic.json")
+    src = os.path.join(ROOT, "paper_1108_1320_amd", "csrc", "k_fft_mac.hip")
+    if not os.path.exists(rec_path):
+        return None
+    rec = json.load(open(rec_path))
+    if rec.get("fft_mac_source_sha256_16") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
+        return None
+    for r in rec.get("batched_records", []):
+        if r["tuning"] == tuning:
+            return r["read_bytes"] + r["write_bytes"]
+    return None
+
+
 def batched_roofline(out, ws):
     """Nominal FFT + MAC flops of every product of the batch over the graph
     replay time: the replay also holds the layout, count-sketch, inverse-FFT
     and diagonal kernels, so this is a lower bound on the spectral kernels'
-    own rate."""
+    own rate.  `traffic`: the spectral kernels' HBM bytes per replay."""
     flop = sum(nominal_fft_mac_flop(w.m, w.b, w.d) for w in ws)
     ms = out["graph_replay_ms"]
     tf = flop / (ms * 1e-3) / 1e12
     return {"kernel": "fft_mac (whole graph replay)", "bound": "alu", "achieved": round(tf, 3),
             "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tf / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": None, "flop_per_launch": flop, "avg_launch_ms": ms}
+            "traffic": batched_traffic_record(out.get("tuning")),
+            "traffic_unit": "bytes per graph replay, spectral kernels only (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                            "copy-calibrated)",
+            "flop_per_launch": flop, "avg_launch_ms": ms}
 
 
 # Steps and warm-up of the other benchmark workloads in the default run,
@@ -543,7 +572,11 @@ def main():
             B = A.clone()
             dev.append((A, B))
             probs.append(cmm.problem(A, B, w.b, w.d, seed=w.seed, dtype=w.dtype, subtract_diag=True))
+        if args.tune_cache and os.path.exists(args.tune_cache):
+            ctx.load_tuning(args.tune_cache)
         bt = cmm.Batch(ctx, probs, autotune=True, keep=dev)
+        if args.tune_cache and not os.path.exists(args.tune_cache):
+            ctx.save_tuning(args.tune_cache)
         bt.run()
         torch.cuda.synchronize()
         ms = []
@@ -555,8 +588,9 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
+        classes = sorted({(w.b, W.next_pow2(w.n1)) for w in ws})
         print(json.dumps({"replays": args.replay_trace, "replay_ms": [round(x, 3) for x in ms],
-                          "products": len(ws)}), flush=True)
+                          "products": len(ws), "tuning": batched_tuning(ctx, classes)}), flush=True)
         bt.free()
         ctx.close()
         return

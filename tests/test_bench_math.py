@@ -59,6 +59,22 @@ def test_traffic_record_only_for_its_workload():
         assert bench.traffic_record(other, geo) is None     # same workload, other operand format
 
 
+def test_batched_traffic_record_only_for_its_tuning():
+    import json
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", "fft_mac_traffic.json")
+    data = json.load(open(rec))
+    src = os.path.join(ROOT, "paper_1108_1320_amd", "csrc", "k_fft_mac.hip")
+    fresh = data["fft_mac_source_sha256_16"] == hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for r in data.get("batched_records", []):
+        t = bench.batched_traffic_record(r["tuning"])
+        assert (t == r["read_bytes"] + r["write_bytes"] and t > 0) if fresh else (t is None)
+        other = {k: [v[0] - 1] + list(v[1:]) for k, v in r["tuning"].items()}
+        assert bench.batched_traffic_record(other) is None   # another geometry of some class
+    assert bench.batched_traffic_record({"b=1,n<=1": [1, 1, 1]}) is None
+    assert bench.batched_traffic_record(None) is None
+
+
 def test_multi_gpu_request_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
