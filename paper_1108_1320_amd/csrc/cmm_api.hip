@@ -311,10 +311,11 @@ cmm::Geometry make_geometry(int64_t b, int d, int64_t m, const cmm::Tuning& tu) 
   g.rblocks = g.R > 1 ? g.R / 2 : 1;
   const int64_t base = (int64_t)d * g.rblocks;
   const int kmax = std::max(1, std::min(tu.kmax, cmm::kMaxKPerBlock));
+  // k-splits: at least 2048 spectral blocks per product (four rounds of the
+  // chip's 512 block slots), at most kmax k per block, at least one k each
   int64_t ks = std::max<int64_t>(1, (2048 + base - 1) / base);
   ks = std::max<int64_t>(ks, (m + kmax - 1) / kmax);
   ks = std::min<int64_t>(ks, m);
-  while (ks < m && (base * ks) % 8 != 0) ++ks;
   g.KS = (int)std::max<int64_t>(1, ks);
   g.cs_blocks = std::max(1, tu.cs_blocks);
   return g;

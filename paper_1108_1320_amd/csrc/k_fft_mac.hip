@@ -48,18 +48,6 @@ template <int T> __device__ __forceinline__ int own(int jbase, int j, int q) {
   else return sw(j + T * q);
 }
 
-// Workgroups are dealt to the eight XCDs in turn (XCD = block id mod 8), and
-// each XCD has its own L2.  Logical tile order puts the rows of one
-// (repetition, k-range) next to each other, and they read the same
-// sketches, so XCD x is given one contiguous range of logical tiles: the
-// first nwg mod 8 XCDs take nwg div 8 + 1 tiles and the others nwg div 8.
-// A bijection on [0, nwg) for every grid size.
-__device__ __forceinline__ int xcd_tile(int bid, int nwg) {
-  const int x = bid & 7, i = bid >> 3;
-  const int q = nwg >> 3, r = nwg & 7;
-  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
-
 struct FftArgs {
   const float* SA0; const float* SA1;
   const uint32_t* ent0; const uint32_t* ent1;
@@ -70,7 +58,7 @@ struct FftArgs {
   const float2* tw;        // omega_b^x for x < b
   float2* Ppart;
   int64_t b;
-  int R, rows, nrow, roff, d, m, KS, nwg, remap;
+  int R, rows, nrow, roff, d, m, KS;
 };
 
 // LDS element at byte offset `off` (fold entries and stage writes carry byte
@@ -388,8 +376,7 @@ __device__ __forceinline__ void fold_all(Batch<kU>& a, unsigned long long* Z, co
 template <int L, int kG>
 __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac_pair(FftArgs a) {
   typedef FftShape<L> F;
-  const int bid = blockIdx.x;
-  const int logical = a.remap ? xcd_tile(bid, a.nwg) : bid;
+  const int logical = blockIdx.x;
   const int ks = logical % a.KS;
   const int t = logical / a.KS;
   constexpr int C = F::C, T = F::T, G = F::G, kU = F::U;
@@ -561,8 +548,12 @@ __global__ __launch_bounds__(FftShape<L>::T, 2) void k_fft_mac(FftArgs a) {
   float2* wf = tm + F::NMID;         // omega_16R^(f1 v), v < 16 R
   static_assert(F::S <= 4, "at most two middle stages");
 
-  const int bid = blockIdx.x;
-  const int logical = a.remap ? xcd_tile(bid, a.nwg) : bid;
+  // Tile order (t, ks, f1), row fastest.  Workgroups are dealt to the eight
+  // XCDs in turn, so the rows of one (repetition, k-range), which read the
+  // same sketches, run on different XCDs at about the same time.  Grouping
+  // them on one XCD so that they share its L2 cuts the reads beyond L2
+  // sixfold but makes this kernel 2.5-5 % slower at 4096-point rows.
+  const int logical = blockIdx.x;
   const int f1 = logical % a.nrow + a.roff;
   const int tmp = logical / a.nrow;
   const int ks = tmp % a.KS;
@@ -696,19 +687,16 @@ static hipError_t launch_LG(FftArgs a, const Geometry& g, hipStream_t s, const O
     if ((e = hipStreamWaitEvent(ov->aux, ov->fork, 0)) != hipSuccess) return e;
   }
   if (g.R > 1) {
-    a.nwg = g.d * g.KS;
-    a.remap = 1;
-    hipLaunchKernelGGL((k_fft_mac_pair<L, kG>), dim3(a.nwg), dim3(F::T), lds, fork ? ov->aux : s, a);
+    hipLaunchKernelGGL((k_fft_mac_pair<L, kG>), dim3(g.d * g.KS), dim3(F::T), lds, fork ? ov->aux : s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (fork && (e = hipEventRecord(ov->join, ov->aux)) != hipSuccess) return e;
   a.nrow = g.R > 1 ? g.R / 2 - 1 : 1;
   a.roff = g.R > 1 ? 1 : 0;
   if (a.nrow > 0) {
-    a.nwg = g.d * g.KS * a.nrow;
-    a.remap = 1;
-    if (g.R > 1) hipLaunchKernelGGL((k_fft_mac<L, kG, false>), dim3(a.nwg), dim3(F::T), lds, s, a);
-    else hipLaunchKernelGGL((k_fft_mac<L, 4, true>), dim3(a.nwg), dim3(F::T), lds, s, a);
+    const int nwg = g.d * g.KS * a.nrow;
+    if (g.R > 1) hipLaunchKernelGGL((k_fft_mac<L, kG, false>), dim3(nwg), dim3(F::T), lds, s, a);
+    else hipLaunchKernelGGL((k_fft_mac<L, 4, true>), dim3(nwg), dim3(F::T), lds, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (fork) e = hipStreamWaitEvent(s, ov->join, 0);
@@ -740,7 +728,7 @@ hipError_t launch_fft_mac(const Geometry& g, const SideDesc& sa, const SideDesc&
   a.Lcap0 = sa.Lcap; a.Lcap1 = sb.Lcap; a.Lrow0 = sa.Lrow; a.Lrow1 = sb.Lrow;
   a.tw = tw32; a.Ppart = Ppart; a.b = g.b;
   a.R = g.R; a.rows = g.rows; a.d = g.d; a.m = g.m; a.KS = g.KS;
-  a.nrow = 1; a.roff = 0; a.nwg = 0; a.remap = 0;
+  a.nrow = 1; a.roff = 0;
   const int64_t n_max = std::max<int64_t>(sa.n, sb.n);
   switch (g.log2c) {
     case 4: return launch_L<4>(a, g, n_max, s, ov);
